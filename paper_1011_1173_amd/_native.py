@@ -1,0 +1,72 @@
+"""ctypes binding of libcholmod_mi355x.so (argument marshalling only).
+
+Every function here mirrors a C entry point of include/cholmod_mi355x.h.
+All arithmetic runs in the HIP kernels of the library; if the library is
+missing, loading fails loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcholmod_mi355x.so")
+
+OK, ERR_ARG, ERR_NOT_PD, ERR_BAD_DIAG, ERR_HIP = 0, -1, -2, -3, -4
+FLAG_EXACT, FLAG_BLOCKED = 1, 2
+F64, F32S = 0, 1
+INFO_NONE = (1 << 63) - 1
+
+EXPORTS = (
+    "cholmod_version", "cholmod_status_string", "cholmod_decode_info",
+    "cholmod_workspace_bytes", "cholmod_update", "cholmod_update_async",
+    "cholmod_update_ex",
+)
+
+_lib = None
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+def load():
+    """Load the built library (raises LibraryMissing if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryMissing("%s is not built; run python -m paper_1011_1173_amd.build" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    p, i64, ci, cu, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint,
+                          ctypes.c_size_t)
+    lib.cholmod_version.argtypes = []
+    lib.cholmod_version.restype = ci
+    lib.cholmod_status_string.argtypes = [ci]
+    lib.cholmod_status_string.restype = ctypes.c_char_p
+    lib.cholmod_decode_info.argtypes = [i64, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.cholmod_decode_info.restype = ci
+    lib.cholmod_workspace_bytes.argtypes = [i64, i64, ci]
+    lib.cholmod_workspace_bytes.restype = sz
+    lib.cholmod_update.argtypes = [p, p, i64, i64, i64, ci, p]
+    lib.cholmod_update.restype = ci
+    lib.cholmod_update_async.argtypes = [p, p, i64, i64, i64, ci, p, sz, p, p]
+    lib.cholmod_update_async.restype = ci
+    lib.cholmod_update_ex.argtypes = [p, p, i64, i64, i64, ci, cu, p, sz, p, p]
+    lib.cholmod_update_ex.restype = ci
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    return load().cholmod_status_string(int(code)).decode()
+
+
+def decode_info(info: int, k: int):
+    row, col = ctypes.c_int64(-1), ctypes.c_int64(-1)
+    st = load().cholmod_decode_info(int(info), int(k), ctypes.byref(row), ctypes.byref(col))
+    return st, row.value, col.value
+
+
+def workspace_bytes(n: int, k: int, dtype: int = F64) -> int:
+    return int(load().cholmod_workspace_bytes(int(n), int(k), int(dtype)))

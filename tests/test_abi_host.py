@@ -1,0 +1,103 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+declared in include/cholmod_mi355x.h, and rejects bad arguments on the host
+before any HIP call (so these run without a GPU and compute nothing)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cholmod_mi355x.h")
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_1011_1173_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        from paper_1011_1173_amd import build
+        build.build()
+    _native.load()
+    return _native
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cholmod_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(nat):
+    names = declared_functions()
+    assert len(names) >= 7
+    lib = ctypes.CDLL(nat.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(nat.EXPORTS) == names
+
+
+def test_version_and_strings(nat):
+    lib = nat.load()
+    assert lib.cholmod_version() >= 100
+    for code in (0, -1, -2, -3, -4):
+        assert len(nat.status_string(code)) >= 2
+    assert nat.status_string(12345) == "unknown status"
+
+
+def test_decode_info(nat):
+    assert nat.decode_info(nat.INFO_NONE, 16) == (0, -1, -1)
+    # index 37 (row 2, col 5 with k = 16), code NOT_PD = 1
+    assert nat.decode_info((37 << 2) | 1, 16) == (nat.ERR_NOT_PD, 2, 5)
+    assert nat.decode_info((48 << 2) | 2, 16) == (nat.ERR_BAD_DIAG, 3, 0)
+
+
+def test_workspace_bytes(nat):
+    assert nat.workspace_bytes(-1, 4) == 0
+    assert nat.workspace_bytes(4, -1) == 0
+    assert nat.workspace_bytes(10, 2, 7) == 0
+    a = nat.workspace_bytes(100, 16)
+    b = nat.workspace_bytes(200, 16)
+    c = nat.workspace_bytes(200, 32)
+    assert 0 < a < b < c
+    assert a % 256 == 0 and b % 256 == 0
+    assert nat.workspace_bytes(100, 16, nat.F32S) < a
+    # private copy of V plus one rotation record per row and column
+    assert a >= 100 * 16 * 8 + 100 * 16 * 32
+    assert nat.workspace_bytes(0, 0) > 0
+
+
+FAKE = ctypes.c_void_p(0x100000)  # never dereferenced: validation fails first
+
+
+def _ex(nat, L=FAKE, V=FAKE, n=8, k=2, ldl=8, sigma=1, flags=0, ws=FAKE, wsb=1 << 20,
+        info=FAKE):
+    return nat.load().cholmod_update_ex(L, V, n, k, ldl, sigma, flags, ws, wsb, info, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n=-1), dict(k=-1), dict(ldl=7), dict(ldl=0, n=0), dict(sigma=0), dict(sigma=2),
+    dict(L=None), dict(V=None), dict(ws=None), dict(wsb=16), dict(info=None),
+    dict(info=ctypes.c_void_p(0x100004)), dict(ws=ctypes.c_void_p(0x100010)), dict(flags=64),
+])
+def test_bad_arguments_rejected_on_host(nat, kw):
+    assert _ex(nat, **kw) == nat.ERR_ARG
+
+
+def test_bad_arguments_sync_and_async(nat):
+    lib = nat.load()
+    assert lib.cholmod_update(FAKE, FAKE, 8, 2, 4, 1, None) == nat.ERR_ARG
+    assert lib.cholmod_update(FAKE, FAKE, 8, 2, 8, 0, None) == nat.ERR_ARG
+    assert lib.cholmod_update(None, FAKE, 8, 2, 8, 1, None) == nat.ERR_ARG
+    assert lib.cholmod_update_async(FAKE, None, 8, 2, 8, 1, FAKE, 1 << 20, FAKE, None) == nat.ERR_ARG
+    assert lib.cholmod_update_async(FAKE, FAKE, 8, 2, 8, -1, FAKE, 10, FAKE, None) == nat.ERR_ARG
+
+
+def test_python_binding_rejects_bad_tensors():
+    import torch
+    import paper_1011_1173_amd as chm
+    L = torch.eye(4, dtype=torch.float64)
+    V = torch.ones(4, 1, dtype=torch.float64)
+    with pytest.raises(chm.ArgumentError):
+        chm.update(L, V, 1)  # CPU tensors are not accepted
+    with pytest.raises(chm.ArgumentError):
+        chm.update(L.float(), V.float(), 1)
