@@ -14,6 +14,10 @@
 namespace chm {
 hipError_t run_blocked(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
                        double sg, Coef* T, int64_t* info, int64_t* stop, bool exact);
+hipError_t run_persist(hipStream_t st, double* L, int64_t n, int64_t ldl, const double* V,
+                       int64_t k, double sg, Coef* Td, double* Wh, int* ctrl, int64_t* info);
+size_t persist_table_bytes(int64_t n, int64_t k);
+size_t persist_handoff_bytes(int64_t n, int64_t k);
 
 namespace {
 
@@ -23,11 +27,14 @@ constexpr int64_t kKPass = 64;  // V columns per pass of the blocked schedule
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout (all offsets 256-byte aligned):
-//   [0, 256)         control words: stop row (int64)
-//   W                n*k private copy of V (row-major, same layout as V)
-//   T                n*min(k,64) rotation records {c, s, 1/c, -}
+//   [0, 256)         control words: stop row (int64), progress and tile
+//                    counter of the single-launch schedule (int32 at +64)
+//   W                n*k private copy of V (blocked schedule)
+//   T                n*min(k,64) rotation records {c, s, 1/c, -} (blocked)
+//   Td               diagonal-major rotation records (single-launch schedule)
+//   Wh               hand-off buffer of the single-launch schedule
 struct WsLayout {
-  size_t ctrl = 0, w = 0, t = 0, total = 0;
+  size_t ctrl = 0, w = 0, t = 0, td = 0, wh = 0, total = 0;
 };
 
 bool mul_ok(int64_t a, int64_t b, int64_t lim) { return a == 0 || b <= lim / a; }
@@ -43,7 +50,9 @@ bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out) {
   L.w = kAlign;
   L.t = L.w + align_up((size_t)(n * k) * es);
   const int64_t kp = k < kKPass ? k : kKPass;
-  L.total = L.t + align_up((size_t)(n * kp) * sizeof(Coef));
+  L.td = L.t + align_up((size_t)(n * kp) * sizeof(Coef));
+  L.wh = L.td + align_up(persist_table_bytes(n, k));
+  L.total = L.wh + align_up(persist_handoff_bytes(n, k));
   *out = L;
   return true;
 }
@@ -85,7 +94,11 @@ int enqueue_f64(double* L, const double* V, int64_t n, int64_t k, int64_t ldl, i
   int64_t* stop_row = (int64_t*)(base + lay.ctrl);
   double* W = (double*)(base + lay.w);
   Coef* T = (Coef*)(base + lay.t);
-  const int64_t count = n * k;
+  const bool exact = (flags & CHOLMOD_FLAG_EXACT) != 0;
+  const bool blocked = exact || (flags & CHOLMOD_FLAG_BLOCKED) != 0;
+  // the blocked schedule works on a private copy of V; the single-launch
+  // schedule reads V directly
+  const int64_t count = blocked ? n * k : 0;
   unsigned grid = (unsigned)((count + 255) / 256);
   if (grid < 1) grid = 1;
   if (grid > 4096) grid = 4096;
@@ -93,8 +106,13 @@ int enqueue_f64(double* L, const double* V, int64_t n, int64_t k, int64_t ldl, i
   if (hipGetLastError() != hipSuccess) return CHOLMOD_ERR_HIP;
   if (n == 0 || k == 0) return CHOLMOD_OK;
   const double sg = (double)sigma;
-  const bool exact = (flags & CHOLMOD_FLAG_EXACT) != 0;
-  hipError_t e = run_blocked(st, L, n, ldl, W, k, sg, T, d_info, stop_row, exact);
+  hipError_t e;
+  if (blocked) {
+    e = run_blocked(st, L, n, ldl, W, k, sg, T, d_info, stop_row, exact);
+  } else {
+    e = run_persist(st, L, n, ldl, V, k, sg, (Coef*)(base + lay.td), (double*)(base + lay.wh),
+                    (int*)(base + lay.ctrl + 64), d_info);
+  }
   return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
 }
 
@@ -138,7 +156,7 @@ int cholmod_decode_info(int64_t info, int64_t k, int64_t* row, int64_t* col) {
   }
   if (code == kCodeNotPD) return CHOLMOD_ERR_NOT_PD;
   if (code == kCodeBadDiag) return CHOLMOD_ERR_BAD_DIAG;
-  return CHOLMOD_ERR_ARG;
+  return CHOLMOD_ERR_HIP;  // a bounded device-side wait gave up
 }
 
 size_t cholmod_workspace_bytes(int64_t n, int64_t k, int dtype) {

@@ -35,7 +35,7 @@ struct alignas(32) Coef {
 };
 
 // Info word: min over failures of (index << 2 | code); INT64_MAX = none.
-enum : int64_t { kCodeNotPD = 1, kCodeBadDiag = 2 };
+enum : int64_t { kCodeNotPD = 1, kCodeBadDiag = 2, kCodeTimeout = 3 };
 __device__ __forceinline__ int64_t info_key(int64_t index, int64_t code) {
   return (index << 2) | code;
 }

@@ -201,3 +201,20 @@ def test_sync_entry_point_and_python_errors(orc):
     with pytest.raises(chm.NotPositiveDefinite) as ei:
         chm.update(Ld, Vbad, -1)
     assert (ei.value.row, ei.value.col) == (5, 0)
+
+
+# ----------------------------------------------------------------- schedules agree bit for bit
+@pytest.mark.parametrize("n,k,sigma", [
+    (1, 1, 1), (2, 2, -1), (3, 16, 1), (17, 5, 1), (18, 16, -1), (20, 3, 1), (63, 8, -1),
+    (64, 16, 1), (65, 1, -1), (100, 15, 1), (129, 16, -1), (257, 7, 1), (1000, 16, 1),
+    (1500, 2, -1), (2049, 16, -1),
+])
+def test_single_launch_schedule_equals_blocked_schedule_bitwise(orc, n, k, sigma):
+    """The single-launch (default) and per-block schedules run the same
+    Compute/Apply arithmetic in the same per-element order: identical bits."""
+    print_case("schedules", n=n, k=k, sigma=sigma)
+    L, V = inputs_for(orc, n, k, 3000 + n + k, sigma)
+    a, sa, _, _ = run_gpu(L, V, sigma)
+    b, sb, _, _ = run_gpu(L, V, sigma, blocked=True)
+    assert sa == 0 and sb == 0
+    assert np.array_equal(a, b), "max |diff| = %g" % np.abs(a - b).max()
