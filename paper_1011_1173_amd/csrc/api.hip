@@ -14,10 +14,8 @@
 namespace chm {
 hipError_t run_blocked(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
                        double sg, Coef* T, int64_t* info, int64_t* stop, bool exact);
-hipError_t run_persist(hipStream_t st, double* L, int64_t n, int64_t ldl, const double* V,
-                       int64_t k, double sg, Coef* Td, double* Wh, int* ctrl, int64_t* info);
-size_t persist_table_bytes(int64_t n, int64_t k);
-size_t persist_handoff_bytes(int64_t n, int64_t k);
+hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
+                      double sg, Coef* T, int64_t* info, int64_t* stop, double* sink);
 
 namespace {
 
@@ -27,14 +25,12 @@ constexpr int64_t kKPass = 64;  // V columns per pass of the blocked schedule
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout (all offsets 256-byte aligned):
-//   [0, 256)         control words: stop row (int64), progress and tile
-//                    counter of the single-launch schedule (int32 at +64)
-//   W                n*k private copy of V (blocked schedule)
-//   T                n*min(k,64) rotation records {c, s, 1/c, -} (blocked)
-//   Td               diagonal-major rotation records (single-launch schedule)
-//   Wh               hand-off buffer of the single-launch schedule
+//   [0, 256)         control words: stop row (int64) at 0, a 64-double sink
+//                    (absorbs loads and stores of idle lanes) after it
+//   W                n*k private copy of V
+//   T                n*max(16, min(k, 64)) rotation records {c, s, 1/c, -}
 struct WsLayout {
-  size_t ctrl = 0, w = 0, t = 0, td = 0, wh = 0, total = 0;
+  size_t ctrl = 0, sink = 0, w = 0, t = 0, total = 0;
 };
 
 bool mul_ok(int64_t a, int64_t b, int64_t lim) { return a == 0 || b <= lim / a; }
@@ -47,12 +43,12 @@ bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out) {
   const size_t es = dtype == CHOLMOD_F64 ? 8 : 4;
   WsLayout L;
   L.ctrl = 0;
-  L.w = kAlign;
+  L.sink = 64;
+  L.w = 2 * kAlign + 256;  // control words + 64-double sink
   L.t = L.w + align_up((size_t)(n * k) * es);
-  const int64_t kp = k < kKPass ? k : kKPass;
-  L.td = L.t + align_up((size_t)(n * kp) * sizeof(Coef));
-  L.wh = L.td + align_up(persist_table_bytes(n, k));
-  L.total = L.wh + align_up(persist_handoff_bytes(n, k));
+  int64_t kp = k < kKPass ? k : kKPass;
+  if (kp < 16) kp = 16;
+  L.total = L.t + align_up((size_t)(n * kp) * sizeof(Coef));
   *out = L;
   return true;
 }
@@ -96,9 +92,7 @@ int enqueue_f64(double* L, const double* V, int64_t n, int64_t k, int64_t ldl, i
   Coef* T = (Coef*)(base + lay.t);
   const bool exact = (flags & CHOLMOD_FLAG_EXACT) != 0;
   const bool blocked = exact || (flags & CHOLMOD_FLAG_BLOCKED) != 0;
-  // the blocked schedule works on a private copy of V; the single-launch
-  // schedule reads V directly
-  const int64_t count = blocked ? n * k : 0;
+  const int64_t count = n * k;  // both schedules work on a private copy of V
   unsigned grid = (unsigned)((count + 255) / 256);
   if (grid < 1) grid = 1;
   if (grid > 4096) grid = 4096;
@@ -110,8 +104,7 @@ int enqueue_f64(double* L, const double* V, int64_t n, int64_t k, int64_t ldl, i
   if (blocked) {
     e = run_blocked(st, L, n, ldl, W, k, sg, T, d_info, stop_row, exact);
   } else {
-    e = run_persist(st, L, n, ldl, V, k, sg, (Coef*)(base + lay.td), (double*)(base + lay.wh),
-                    (int*)(base + lay.ctrl + 64), d_info);
+    e = run_sysblk(st, L, n, ldl, W, k, sg, T, d_info, stop_row, (double*)(base + lay.sink));
   }
   return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
 }

@@ -209,9 +209,11 @@ def test_sync_entry_point_and_python_errors(orc):
     (64, 16, 1), (65, 1, -1), (100, 15, 1), (129, 16, -1), (257, 7, 1), (1000, 16, 1),
     (1500, 2, -1), (2049, 16, -1),
 ])
-def test_single_launch_schedule_equals_blocked_schedule_bitwise(orc, n, k, sigma):
-    """The single-launch (default) and per-block schedules run the same
-    Compute/Apply arithmetic in the same per-element order: identical bits."""
+def test_chain_schedule_equals_row_schedule_bitwise(orc, n, k, sigma):
+    """The default fast schedule (64-row blocks run as a systolic chain in one
+    workgroup, then a column-parallel Apply) and the per-row fast schedule run
+    the same Compute/Apply arithmetic in the same per-element order: their
+    results must be identical bit for bit."""
     print_case("schedules", n=n, k=k, sigma=sigma)
     L, V = inputs_for(orc, n, k, 3000 + n + k, sigma)
     a, sa, _, _ = run_gpu(L, V, sigma)
