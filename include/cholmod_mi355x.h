@@ -131,6 +131,117 @@ int cholmod_update_ex(double *L, const double *V, int64_t n, int64_t k, int64_t 
                       int sigma, unsigned flags, void *ws, size_t ws_bytes,
                       int64_t *d_info, cholmod_stream_t stream);
 
+/*
+ * FP32-storage mode: the same modification (Algorithm 1) with L and V
+ * stored in binary32.  The rows of each 64-row diagonal block -- every
+ * Compute (w, c, s, 1/c) and the Apply inside the block -- are evaluated in
+ * binary64 from the stored values and rounded to binary32 when stored; the
+ * Apply of a block's rotations to the columns right of the next block runs
+ * in binary32 with the coefficients rounded to binary32.  Accuracy: the
+ * relative Frobenius distance to the binary64 factor of the same (binary32)
+ * inputs is about 1e-6 (bound tested: 1e-5).  Halves the memory traffic;
+ * the serial chain is unchanged.  Layout, ownership and error reporting are
+ * those of the FP64 entry points with float in place of double; there is no
+ * EXACT mode.
+ *   cholmod_update_f32s: synchronous, library-owned workspace.
+ *   cholmod_update_f32s_async: caller workspace of at least
+ *     cholmod_workspace_bytes(n, k, CHOLMOD_F32S) bytes, device info word.
+ */
+int cholmod_update_f32s(float *L, const float *V, int64_t n, int64_t k, int64_t ldl,
+                        int sigma, cholmod_stream_t stream);
+int cholmod_update_f32s_async(float *L, const float *V, int64_t n, int64_t k, int64_t ldl,
+                              int sigma, void *ws, size_t ws_bytes, int64_t *d_info,
+                              cholmod_stream_t stream);
+
+/*
+ * Batched modification of many independent factors (uneven n, k, sigma and
+ * storage type) on one stream.  Each factor is modified exactly as by the
+ * single-factor entry point of its storage type (same blocking, same
+ * operations), so its result is bit for bit the one it gets alone.  The
+ * batch runs as one preparation launch plus one launch per step, where
+ * step s processes block s of every factor that has one (longest factor
+ * first); the blocks of different factors run concurrently.
+ *   descs     HOST array of `count` descriptors (read during the call only);
+ *             the factors must not overlap in memory
+ *   count     0 .. 65535 (0 is a no-op)
+ *   ws        device workspace of at least
+ *             cholmod_workspace_bytes_batched(descs, count) bytes, 256-byte
+ *             aligned, not used by other work until the stream has passed
+ *             this batch
+ *   d_info    device int64[count]: raw info word of each factor (decode with
+ *             cholmod_decode_info and that factor's k); a failure in one
+ *             factor leaves the others unaffected
+ * Returns CHOLMOD_OK when enqueued, CHOLMOD_ERR_ARG (nothing enqueued) if any
+ * descriptor is invalid, or CHOLMOD_ERR_HIP.  Does not wait for the work; the
+ * library keeps a pinned staging buffer per device for the batch tables.
+ */
+typedef struct cholmod_desc {
+  void *L;          /* device double* (CHOLMOD_F64) or float* (CHOLMOD_F32S) */
+  const void *V;    /* device, (n, k) row-major, unchanged */
+  int64_t n, k, ldl;
+  int32_t sigma;    /* +1 update, -1 downdate */
+  int32_t dtype;    /* CHOLMOD_F64 or CHOLMOD_F32S */
+} cholmod_desc;
+
+/* Workspace bytes of a batch (0 if any descriptor is invalid). */
+size_t cholmod_workspace_bytes_batched(const cholmod_desc *descs, int64_t count);
+
+int cholmod_update_batched(const cholmod_desc *descs, int64_t count, void *ws, size_t ws_bytes,
+                           int64_t *d_info, cholmod_stream_t stream);
+
+/*
+ * Served mode: factors registered once, then a stream of requests (one
+ * update or downdate of one factor by a caller-owned V) batched
+ * continuously onto one GPU by a library worker thread.  Requests of one
+ * factor run in submission order; requests of different factors run
+ * concurrently in batches (cholmod_update_batched's schedule, so each
+ * result is bit for bit the single-factor result).  The server owns one
+ * non-blocking stream on cfg->device, two batch slots of cfg->ws_bytes
+ * device workspace each (its HBM budget besides the factors), and pinned
+ * staging memory; all are allocated by cholmod_server_create.
+ */
+typedef struct cholmod_server cholmod_server;
+
+typedef struct cholmod_server_cfg {
+  size_t ws_bytes;    /* device workspace per batch slot (>= 4096); a batch takes
+                         as many waiting requests as fit (cholmod_workspace_bytes_batched) */
+  int32_t max_batch;  /* most requests per batch (0 = 256, at most 65535) */
+  int32_t device;     /* HIP device of the factors */
+} cholmod_server_cfg;
+
+/* Create a server and start its worker.  CHOLMOD_ERR_ARG for a bad cfg. */
+int cholmod_server_create(const cholmod_server_cfg *cfg, cholmod_server **out);
+
+/*
+ * Register a device factor (caller-owned, stays valid until the server is
+ * destroyed; only the server modifies it meanwhile).  *id receives its index.
+ */
+int cholmod_server_add_factor(cholmod_server *srv, void *L, int64_t n, int64_t ldl, int dtype,
+                              int32_t *id);
+
+/*
+ * Queue the modification of factor `id` by V (device, (n, k) row-major, in
+ * the factor's storage type; caller-owned and unchanged until the request
+ * completes).  *ticket identifies the request.  Never blocks on the GPU.
+ */
+int cholmod_server_submit(cholmod_server *srv, int32_t id, const void *V, int64_t k, int sigma,
+                          uint64_t *ticket);
+
+/*
+ * Non-blocking: returns 1 while the request is pending; 0 once it has
+ * completed, with *status its result (CHOLMOD_OK, CHOLMOD_ERR_NOT_PD, ...;
+ * CHOLMOD_ERR_ARG if it could not fit the workspace) and *latency_s the
+ * host time from submission to completion; the ticket is then released.
+ * CHOLMOD_ERR_ARG for an unknown ticket.
+ */
+int cholmod_server_poll(cholmod_server *srv, uint64_t ticket, int *status, double *latency_s);
+
+/* Wait until every submitted request has completed. */
+int cholmod_server_drain(cholmod_server *srv);
+
+/* Drain, stop the worker and free the server's resources. */
+int cholmod_server_destroy(cholmod_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,8 +18,9 @@ from . import _native
 from ._native import (ERR_ARG, ERR_BAD_DIAG, ERR_HIP, ERR_NOT_PD, F32S, F64, FLAG_BLOCKED,
                       FLAG_EXACT, INFO_NONE, OK, LibraryMissing)
 
-__all__ = ["update", "update_async", "workspace_bytes", "CholmodError", "ArgumentError",
-           "NotPositiveDefinite", "BadDiagonal", "HipError", "LibraryMissing", "Pending"]
+__all__ = ["update", "update_async", "update_batched", "update_batched_async",
+           "workspace_bytes", "CholmodError", "ArgumentError", "NotPositiveDefinite",
+           "BadDiagonal", "HipError", "LibraryMissing", "Pending", "PendingBatch", "Server"]
 
 
 class CholmodError(RuntimeError):
@@ -69,11 +70,11 @@ def workspace_bytes(n: int, k: int, dtype: int = F64) -> int:
     return _native.workspace_bytes(n, k, dtype)
 
 
-def _factor_args(L: torch.Tensor, V: torch.Tensor, dtype: torch.dtype):
+def _factor_args(L: torch.Tensor, V: torch.Tensor):
     if not isinstance(L, torch.Tensor) or not isinstance(V, torch.Tensor):
         raise ArgumentError("L and V must be torch tensors")
-    if L.dtype != dtype or V.dtype != dtype:
-        raise ArgumentError("L and V must have dtype %s" % dtype)
+    if L.dtype not in (torch.float64, torch.float32) or V.dtype != L.dtype:
+        raise ArgumentError("L and V must both be float64, or both float32 (FP32 storage)")
     if L.device.type != "cuda" or V.device != L.device:
         raise ArgumentError("L and V must be on the same GPU")
     if L.dim() != 2 or L.stride(1) != 1 or L.shape[1] < L.shape[0]:
@@ -117,28 +118,167 @@ class Pending:
 def update_async(L: torch.Tensor, V: torch.Tensor, sigma: int, *, exact: bool = False,
                  blocked: bool = False, stream=None, workspace: torch.Tensor | None = None,
                  info: torch.Tensor | None = None) -> Pending:
-    """Enqueue the rank-k modification of L (FP64) on ``stream``; no host sync."""
-    n, k, ldl, V = _factor_args(L, V, torch.float64)
+    """Enqueue the rank-k modification of L on ``stream``; no host sync.
+
+    float64 tensors use cholmod_update_ex (``exact`` / ``blocked`` select the
+    evaluation mode and schedule); float32 tensors use the FP32-storage mode
+    cholmod_update_f32s_async, which has neither option.
+    """
+    n, k, ldl, V = _factor_args(L, V)
+    f32 = L.dtype == torch.float32
+    if f32 and (exact or blocked):
+        raise ArgumentError("FP32 storage has no exact or blocked mode")
     stream = torch.cuda.current_stream(L.device) if stream is None else stream
-    need = workspace_bytes(n, k, F64)
+    need = workspace_bytes(n, k, F32S if f32 else F64)
     if workspace is None:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=L.device)
     if info is None:
         info = torch.empty(1, dtype=torch.int64, device=L.device)
-    flags = (FLAG_EXACT if exact else 0) | (FLAG_BLOCKED if blocked else 0)
-    st = _native.load().cholmod_update_ex(
-        ctypes.c_void_p(L.data_ptr()), ctypes.c_void_p(V.data_ptr()), n, k, ldl, int(sigma),
-        flags, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
-        ctypes.c_void_p(info.data_ptr()), _stream_handle(stream))
+    lib = _native.load()
+    args = (ctypes.c_void_p(L.data_ptr()), ctypes.c_void_p(V.data_ptr()), n, k, ldl, int(sigma))
+    tail = (ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+            ctypes.c_void_p(info.data_ptr()), _stream_handle(stream))
+    if f32:
+        st = lib.cholmod_update_f32s_async(*args, *tail)
+    else:
+        flags = (FLAG_EXACT if exact else 0) | (FLAG_BLOCKED if blocked else 0)
+        st = lib.cholmod_update_ex(*args, flags, *tail)
     _raise_for(st)
     return Pending(k, workspace, info, stream)
 
 
 def update(L: torch.Tensor, V: torch.Tensor, sigma: int, *, exact: bool = False,
            blocked: bool = False, stream=None) -> None:
-    """Overwrite L (upper, FP64, on the GPU) with the factor of L^T L + sigma V V^T.
+    """Overwrite L (upper, on the GPU; float64, or float32 for FP32 storage)
+    with the factor of L^T L + sigma V V^T.
 
     Raises NotPositiveDefinite / BadDiagonal with the first failing (row,
     column), or ArgumentError for bad shapes and types.
     """
     update_async(L, V, sigma, exact=exact, blocked=blocked, stream=stream).wait()
+
+
+class PendingBatch:
+    """An enqueued batch; keeps its workspace and descriptors alive."""
+
+    def __init__(self, ks, ws, info, stream):
+        self.ks, self._ws, self.info, self.stream = ks, ws, info, stream
+
+    def statuses(self):
+        """Wait for the stream; (status, row, col) of every factor."""
+        self.stream.synchronize()
+        raw = self.info.cpu().tolist()
+        return [_native.decode_info(int(r), k) for r, k in zip(raw, self.ks)]
+
+
+def _descs(Ls, Vs, sigmas):
+    if not (len(Ls) == len(Vs) == len(sigmas)):
+        raise ArgumentError("Ls, Vs and sigmas must have the same length")
+    arr = (_native.Desc * max(1, len(Ls)))()
+    ks, dev = [], None
+    for i, (L, V, sg) in enumerate(zip(Ls, Vs, sigmas)):
+        n, k, ldl, V = _factor_args(L, V)
+        if dev is None:
+            dev = L.device
+        elif L.device != dev:
+            raise ArgumentError("all factors of a batch must be on one GPU")
+        arr[i] = _native.Desc(L.data_ptr(), V.data_ptr(), n, k, ldl, int(sg),
+                              F32S if L.dtype == torch.float32 else F64)
+        ks.append(k)
+    return arr, ks, dev
+
+
+def update_batched_async(Ls, Vs, sigmas, *, stream=None, workspace: torch.Tensor | None = None,
+                         info: torch.Tensor | None = None) -> PendingBatch:
+    """Enqueue the modification of every factor Ls[i] by (Vs[i], sigmas[i])
+    (cholmod_update_batched); float64 and float32 factors may be mixed."""
+    arr, ks, dev = _descs(Ls, Vs, sigmas)
+    count = len(ks)
+    if count == 0:
+        raise ArgumentError("empty batch")
+    stream = torch.cuda.current_stream(dev) if stream is None else stream
+    lib = _native.load()
+    need = int(lib.cholmod_workspace_bytes_batched(arr, count))
+    if need == 0:
+        raise ArgumentError("invalid batch")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    if info is None:
+        info = torch.empty(count, dtype=torch.int64, device=dev)
+    st = lib.cholmod_update_batched(arr, count, ctypes.c_void_p(workspace.data_ptr()),
+                                    workspace.numel(), ctypes.c_void_p(info.data_ptr()),
+                                    _stream_handle(stream))
+    _raise_for(st)
+    return PendingBatch(ks, workspace, info, stream)
+
+
+def update_batched(Ls, Vs, sigmas, *, stream=None):
+    """Modify every factor and wait; returns [(status, row, col)] per factor
+    (a numerical failure in one factor does not raise and does not affect
+    the others)."""
+    return update_batched_async(Ls, Vs, sigmas, stream=stream).statuses()
+
+
+class Server:
+    """Served mode (cholmod_server_*): registered factors, submitted requests,
+    continuous batching by a library worker thread.  The Python object keeps
+    every registered factor and every pending V alive."""
+
+    def __init__(self, ws_bytes: int = 1 << 30, max_batch: int = 256, device=None):
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        cfg = _native.ServerCfg(int(ws_bytes), int(max_batch), int(dev.index))
+        h = ctypes.c_void_p()
+        _raise_for(_native.load().cholmod_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h, self.device = h, dev
+        self._factors, self._pending = [], {}
+
+    def add_factor(self, L: torch.Tensor) -> int:
+        n, _, ldl, _ = _factor_args(L, torch.empty((L.shape[0], 0), dtype=L.dtype,
+                                                   device=L.device))
+        fid = ctypes.c_int32(-1)
+        _raise_for(_native.load().cholmod_server_add_factor(
+            self._h, ctypes.c_void_p(L.data_ptr()), n, ldl,
+            F32S if L.dtype == torch.float32 else F64, ctypes.byref(fid)))
+        self._factors.append((L, L.dtype))
+        return fid.value
+
+    def submit(self, fid: int, V: torch.Tensor, sigma: int) -> int:
+        if not 0 <= fid < len(self._factors):
+            raise ArgumentError("unknown factor")
+        L, dt = self._factors[fid]
+        if V.dim() == 1:
+            V = V.view(-1, 1)
+        if V.dtype != dt or V.device != L.device or not V.is_contiguous() or V.shape[0] != L.shape[0]:
+            raise ArgumentError("V must be a contiguous (n, k) tensor of the factor's dtype and device")
+        t = ctypes.c_uint64(0)
+        _raise_for(_native.load().cholmod_server_submit(
+            self._h, int(fid), ctypes.c_void_p(V.data_ptr()), V.shape[1], int(sigma),
+            ctypes.byref(t)))
+        self._pending[t.value] = V
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else (status, latency_s)."""
+        st, lat = ctypes.c_int(0), ctypes.c_double(0.0)
+        rc = _native.load().cholmod_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(st),
+                                                ctypes.byref(lat))
+        if rc == 1:
+            return None
+        _raise_for(rc)
+        self._pending.pop(ticket, None)
+        return st.value, lat.value
+
+    def drain(self):
+        _raise_for(_native.load().cholmod_server_drain(self._h))
+
+    def close(self):
+        if self._h is not None:
+            _raise_for(_native.load().cholmod_server_destroy(self._h))
+            self._h = None
+            self._pending.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -20,8 +20,24 @@ INFO_NONE = (1 << 63) - 1
 EXPORTS = (
     "cholmod_version", "cholmod_status_string", "cholmod_decode_info",
     "cholmod_workspace_bytes", "cholmod_update", "cholmod_update_async",
-    "cholmod_update_ex",
+    "cholmod_update_ex", "cholmod_update_f32s", "cholmod_update_f32s_async",
+    "cholmod_workspace_bytes_batched", "cholmod_update_batched",
+    "cholmod_server_create", "cholmod_server_add_factor", "cholmod_server_submit",
+    "cholmod_server_poll", "cholmod_server_drain", "cholmod_server_destroy",
 )
+
+
+class ServerCfg(ctypes.Structure):
+    """struct cholmod_server_cfg of the header."""
+    _fields_ = [("ws_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+
+class Desc(ctypes.Structure):
+    """struct cholmod_desc of the header."""
+    _fields_ = [("L", ctypes.c_void_p), ("V", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("ldl", ctypes.c_int64), ("sigma", ctypes.c_int32),
+                ("dtype", ctypes.c_int32)]
 
 _lib = None
 
@@ -54,6 +70,29 @@ def load():
     lib.cholmod_update_async.restype = ci
     lib.cholmod_update_ex.argtypes = [p, p, i64, i64, i64, ci, cu, p, sz, p, p]
     lib.cholmod_update_ex.restype = ci
+    lib.cholmod_update_f32s.argtypes = [p, p, i64, i64, i64, ci, p]
+    lib.cholmod_update_f32s.restype = ci
+    lib.cholmod_update_f32s_async.argtypes = [p, p, i64, i64, i64, ci, p, sz, p, p]
+    lib.cholmod_update_f32s_async.restype = ci
+    dp = ctypes.POINTER(Desc)
+    lib.cholmod_workspace_bytes_batched.argtypes = [dp, i64]
+    lib.cholmod_workspace_bytes_batched.restype = sz
+    lib.cholmod_update_batched.argtypes = [dp, i64, p, sz, p, p]
+    lib.cholmod_update_batched.restype = ci
+    lib.cholmod_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(p)]
+    lib.cholmod_server_create.restype = ci
+    lib.cholmod_server_add_factor.argtypes = [p, p, i64, i64, ci, ctypes.POINTER(ctypes.c_int32)]
+    lib.cholmod_server_add_factor.restype = ci
+    lib.cholmod_server_submit.argtypes = [p, ctypes.c_int32, p, i64, ci,
+                                          ctypes.POINTER(ctypes.c_uint64)]
+    lib.cholmod_server_submit.restype = ci
+    lib.cholmod_server_poll.argtypes = [p, ctypes.c_uint64, ctypes.POINTER(ci),
+                                        ctypes.POINTER(ctypes.c_double)]
+    lib.cholmod_server_poll.restype = ci
+    lib.cholmod_server_drain.argtypes = [p]
+    lib.cholmod_server_drain.restype = ci
+    lib.cholmod_server_destroy.argtypes = [p]
+    lib.cholmod_server_destroy.restype = ci
     _lib = lib
     return lib
 

@@ -2,20 +2,28 @@
 // host, workspace layout, schedule selection and the synchronous wrapper.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <numeric>
 #include <vector>
 
 #include "../../include/cholmod_mi355x.h"
+#include "batch.h"
+#include "internal.h"
 #include "rotations.h"
 
 namespace chm {
 hipError_t run_blocked(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
                        double sg, Coef* T, int64_t* info, int64_t* stop, bool exact);
 hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
-                      double sg, Coef* T, int64_t* info, int64_t* stop, double* sink);
+                      double sg, Coef* T, int64_t* info, int64_t* stop);
+hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, float* W, int64_t k,
+                          double sg, void* T, int64_t* info, int64_t* stop);
+hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
+                            const BatchEntry* d_ent, const BatchStep* steps, int64_t nsteps);
 
 namespace {
 
@@ -25,12 +33,11 @@ constexpr int64_t kKPass = 64;  // V columns per pass of the blocked schedule
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout (all offsets 256-byte aligned):
-//   [0, 256)         control words: stop row (int64) at 0, a 64-double sink
-//                    (absorbs loads and stores of idle lanes) after it
+//   [0, 768)         control words: the first failing row (int64) at 0
 //   W                n*k private copy of V
-//   T                n*max(16, min(k, 64)) rotation records {c, s, 1/c, -}
+//   T                n*max(16, min(k, 64)) rotation records of 32 bytes
 struct WsLayout {
-  size_t ctrl = 0, sink = 0, w = 0, t = 0, total = 0;
+  size_t ctrl = 0, w = 0, t = 0, total = 0;
 };
 
 bool mul_ok(int64_t a, int64_t b, int64_t lim) { return a == 0 || b <= lim / a; }
@@ -43,8 +50,7 @@ bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out) {
   const size_t es = dtype == CHOLMOD_F64 ? 8 : 4;
   WsLayout L;
   L.ctrl = 0;
-  L.sink = 64;
-  L.w = 2 * kAlign + 256;  // control words + 64-double sink
+  L.w = 3 * kAlign;  // control words
   L.t = L.w + align_up((size_t)(n * k) * es);
   int64_t kp = k < kKPass ? k : kKPass;
   if (kp < 16) kp = 16;
@@ -53,7 +59,8 @@ bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out) {
   return true;
 }
 
-__global__ void k_prepare(const double* __restrict__ V, double* __restrict__ W, int64_t count,
+template <typename ST>
+__global__ void k_prepare(const ST* __restrict__ V, ST* __restrict__ W, int64_t count,
                           int64_t* __restrict__ info, int64_t* __restrict__ stop_row) {
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i0 == 0) {
@@ -96,7 +103,8 @@ int enqueue_f64(double* L, const double* V, int64_t n, int64_t k, int64_t ldl, i
   unsigned grid = (unsigned)((count + 255) / 256);
   if (grid < 1) grid = 1;
   if (grid > 4096) grid = 4096;
-  hipLaunchKernelGGL(k_prepare, dim3(grid), dim3(256), 0, st, V, W, count, d_info, stop_row);
+  hipLaunchKernelGGL(k_prepare<double>, dim3(grid), dim3(256), 0, st, V, W, count, d_info,
+                     stop_row);
   if (hipGetLastError() != hipSuccess) return CHOLMOD_ERR_HIP;
   if (n == 0 || k == 0) return CHOLMOD_OK;
   const double sg = (double)sigma;
@@ -104,21 +112,228 @@ int enqueue_f64(double* L, const double* V, int64_t n, int64_t k, int64_t ldl, i
   if (blocked) {
     e = run_blocked(st, L, n, ldl, W, k, sg, T, d_info, stop_row, exact);
   } else {
-    e = run_sysblk(st, L, n, ldl, W, k, sg, T, d_info, stop_row, (double*)(base + lay.sink));
+    e = run_sysblk(st, L, n, ldl, W, k, sg, T, d_info, stop_row);
   }
   return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
 }
 
-// Library-owned workspace for the synchronous entry point (one per device).
+int enqueue_f32s(float* L, const float* V, int64_t n, int64_t k, int64_t ldl, int sigma,
+                 void* ws, size_t ws_bytes, int64_t* d_info, hipStream_t st) {
+  int v = validate(L, V, n, k, ldl, sigma);
+  if (v) return v;
+  if (d_info == nullptr) return CHOLMOD_ERR_ARG;
+  if (((uintptr_t)d_info & 7u) != 0) return CHOLMOD_ERR_ARG;
+  WsLayout lay;
+  if (!layout_for(n, k, CHOLMOD_F32S, &lay)) return CHOLMOD_ERR_ARG;
+  if (ws == nullptr || ws_bytes < lay.total) return CHOLMOD_ERR_ARG;
+  if (((uintptr_t)ws % kAlign) != 0) return CHOLMOD_ERR_ARG;
+  char* base = (char*)ws;
+  int64_t* stop_row = (int64_t*)(base + lay.ctrl);
+  float* W = (float*)(base + lay.w);
+  void* T = (void*)(base + lay.t);
+  const int64_t count = n * k;
+  unsigned grid = (unsigned)((count + 255) / 256);
+  if (grid < 1) grid = 1;
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_prepare<float>, dim3(grid), dim3(256), 0, st, V, W, count, d_info,
+                     stop_row);
+  if (hipGetLastError() != hipSuccess) return CHOLMOD_ERR_HIP;
+  if (n == 0 || k == 0) return CHOLMOD_OK;
+  hipError_t e = run_sysblk_f32(st, L, n, ldl, W, k, (double)sigma, T, d_info, stop_row);
+  return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
+}
+
+// Library-owned per-device state: the workspace of the synchronous entry
+// points, and the pinned staging buffer of the batched planner with the event
+// that marks the end of its last upload.
 struct DevWs {
   void* ptr = nullptr;
   size_t bytes = 0;
   int64_t* host_info = nullptr;  // pinned
+  void* stage = nullptr;         // pinned
+  size_t stage_bytes = 0;
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
 };
 std::mutex g_mu;
 std::vector<DevWs> g_ws;
 
+// Synchronous wrapper: library-owned workspace and pinned info word, then
+// enqueue, copy the info word back and wait for the stream.
+template <typename Enqueue>
+int run_sync(int64_t n, int64_t k, int dtype, hipStream_t st, Enqueue enqueue) {
+  WsLayout lay;
+  if (!layout_for(n, k, dtype, &lay)) return CHOLMOD_ERR_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CHOLMOD_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+  DevWs& d = g_ws[dev];
+  const size_t need = lay.total + kAlign;  // + info word
+  if (d.bytes < need) {
+    if (d.ptr) {
+      if (hipDeviceSynchronize() != hipSuccess) return CHOLMOD_ERR_HIP;
+      hipFree(d.ptr);
+      d.ptr = nullptr;
+      d.bytes = 0;
+    }
+    if (hipMalloc(&d.ptr, need) != hipSuccess) return CHOLMOD_ERR_HIP;
+    d.bytes = need;
+  }
+  if (!d.host_info) {
+    if (hipHostMalloc((void**)&d.host_info, sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+      return CHOLMOD_ERR_HIP;
+  }
+  int64_t* d_info = (int64_t*)((char*)d.ptr + lay.total);
+  int rc = enqueue(d.ptr, lay.total, d_info, st);
+  if (rc) return rc;
+  if (hipMemcpyAsync(d.host_info, d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st) !=
+      hipSuccess)
+    return CHOLMOD_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return CHOLMOD_ERR_HIP;
+  return cholmod_decode_info(*d.host_info, k, nullptr, nullptr);
+}
+
+// ------------------------------------------------------------------ batched
+constexpr int64_t kBlock = 64, kPass = 16, kMaxBatch = 65535;
+
+struct BatchPlan {
+  std::vector<BatchFactor> fac;
+  std::vector<BatchEntry> ent;
+  std::vector<BatchStep> steps;
+  size_t off_ent = 0, off_fac_data = 0, table_bytes = 0, total = 0;
+  std::vector<size_t> off_ctrl, off_w, off_t;
+};
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int validate_desc(const cholmod_desc& d) {
+  if (d.dtype != CHOLMOD_F64 && d.dtype != CHOLMOD_F32S) return CHOLMOD_ERR_ARG;
+  return validate(d.L, d.V, d.n, d.k, d.ldl, d.sigma);
+}
+
+// Sizes and (when ws != nullptr) device pointers of a batch; the schedule
+// of each factor is the single-factor one (64-row blocks, 16-column passes).
+int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P) {
+  if (count < 0 || count > kMaxBatch) return CHOLMOD_ERR_ARG;
+  if (count > 0 && descs == nullptr) return CHOLMOD_ERR_ARG;
+  std::vector<int64_t> steps(count), blocks(count);
+  int64_t total_ent = 0, smax = 0;
+  for (int64_t f = 0; f < count; ++f) {
+    const int v = validate_desc(descs[f]);
+    if (v) return v;
+    const cholmod_desc& d = descs[f];
+    blocks[f] = ceil_div(d.n, kBlock);
+    steps[f] = (d.n == 0 || d.k == 0) ? 0 : blocks[f] * ceil_div(d.k, kPass);
+    total_ent += steps[f];
+    smax = std::max(smax, steps[f]);
+  }
+  P->off_ent = align_up((size_t)count * sizeof(BatchFactor));
+  P->table_bytes = P->off_ent + align_up((size_t)total_ent * sizeof(BatchEntry));
+  size_t off = P->table_bytes;
+  P->off_ctrl.resize(count);
+  P->off_w.resize(count);
+  P->off_t.resize(count);
+  for (int64_t f = 0; f < count; ++f) {
+    const cholmod_desc& d = descs[f];
+    WsLayout lay;
+    if (!layout_for(d.n, d.k, d.dtype, &lay)) return CHOLMOD_ERR_ARG;
+    P->off_ctrl[f] = off + lay.ctrl;
+    P->off_w[f] = off + lay.w;
+    P->off_t[f] = off + lay.t;
+    off += lay.total;
+  }
+  P->total = off;
+  if (ws == nullptr) return CHOLMOD_OK;
+  // factor table
+  P->fac.resize(count);
+  for (int64_t f = 0; f < count; ++f) {
+    const cholmod_desc& d = descs[f];
+    BatchFactor& F = P->fac[f];
+    F.L = d.L;
+    F.V = d.V;
+    F.W = ws + P->off_w[f];
+    F.T = ws + P->off_t[f];
+    F.info = nullptr;  // set by the caller
+    F.stop = (int64_t*)(ws + P->off_ctrl[f]);
+    F.n = d.n;
+    F.k = d.k;
+    F.ldl = d.ldl;
+    F.sigma = d.sigma;
+    F.dtype = d.dtype == CHOLMOD_F64 ? kStoreF64 : kStoreF32;
+  }
+  // longest factor first; at step s the active factors are a prefix
+  std::vector<int64_t> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return steps[a] > steps[b]; });
+  P->ent.clear();
+  P->ent.reserve(total_ent);
+  P->steps.assign(smax, BatchStep{});
+  for (int64_t s = 0; s < smax; ++s) {
+    BatchStep& S = P->steps[s];
+    S.off = (int64_t)P->ent.size();
+    int64_t rest = 0;
+    for (int64_t f : order) {
+      if (s >= steps[f]) break;
+      const cholmod_desc& d = descs[f];
+      const int64_t pass = s / blocks[f], b = s % blocks[f];
+      BatchEntry e;
+      e.pc = b * kBlock;
+      e.pa = b > 0 ? e.pc - kBlock : -1;
+      e.m0 = pass * kPass;
+      e.f = (int32_t)f;
+      e.bbc = (int32_t)std::min(kBlock, d.n - e.pc);
+      e.kc = (int32_t)std::min(kPass, d.k - e.m0);
+      e.rest0 = (int32_t)rest;
+      rest += e.pa >= 0 ? ceil_div(d.n - e.pc - e.bbc, kBlock) : 0;
+      P->ent.push_back(e);
+    }
+    S.nent = (int64_t)P->ent.size() - S.off;
+    S.nrest = rest;
+  }
+  return CHOLMOD_OK;
+}
+
 }  // namespace
+
+size_t batch_table_bytes(const cholmod_desc* descs, int64_t count) {
+  BatchPlan P;
+  if (plan_batch(descs, count, nullptr, &P) != CHOLMOD_OK) return 0;
+  return P.table_bytes;
+}
+
+size_t batch_workspace_bytes(const cholmod_desc* descs, int64_t count) {
+  BatchPlan P;
+  if (plan_batch(descs, count, nullptr, &P) != CHOLMOD_OK) return 0;
+  return P.total;
+}
+
+int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_bytes,
+                  int64_t* d_info, hipStream_t st, void* stage, size_t stage_bytes) {
+  BatchPlan P;
+  int rc = plan_batch(descs, count, nullptr, &P);
+  if (rc) return rc;
+  if (count == 0) return CHOLMOD_OK;
+  if (d_info == nullptr || ((uintptr_t)d_info & 7u) != 0) return CHOLMOD_ERR_ARG;
+  if (ws == nullptr || ws_bytes < P.total || ((uintptr_t)ws % kAlign) != 0)
+    return CHOLMOD_ERR_ARG;
+  if (stage == nullptr || stage_bytes < P.table_bytes) return CHOLMOD_ERR_ARG;
+  rc = plan_batch(descs, count, (char*)ws, &P);
+  if (rc) return rc;
+  for (int64_t f = 0; f < count; ++f) P.fac[f].info = d_info + f;
+  char* h = (char*)stage;
+  std::memcpy(h, P.fac.data(), P.fac.size() * sizeof(BatchFactor));
+  if (!P.ent.empty()) std::memcpy(h + P.off_ent, P.ent.data(), P.ent.size() * sizeof(BatchEntry));
+  if (hipMemcpyAsync(ws, h, P.table_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+    return CHOLMOD_ERR_HIP;
+  const BatchFactor* d_fac = (const BatchFactor*)ws;
+  const BatchEntry* d_ent = (const BatchEntry*)((char*)ws + P.off_ent);
+  hipError_t e = run_sysblk_batch(st, d_fac, count, d_ent, P.steps.data(),
+                                  (int64_t)P.steps.size());
+  return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
+}
+
 }  // namespace chm
 
 using namespace chm;
@@ -174,37 +389,67 @@ int cholmod_update(double* L, const double* V, int64_t n, int64_t k, int64_t ldl
                    cholmod_stream_t stream) {
   int v = validate(L, V, n, k, ldl, sigma);
   if (v) return v;
-  WsLayout lay;
-  if (!layout_for(n, k, CHOLMOD_F64, &lay)) return CHOLMOD_ERR_ARG;
+  return run_sync(n, k, CHOLMOD_F64, (hipStream_t)stream,
+                  [&](void* ws, size_t bytes, int64_t* d_info, hipStream_t st) {
+                    return enqueue_f64(L, V, n, k, ldl, sigma, 0u, ws, bytes, d_info, st);
+                  });
+}
+
+int cholmod_update_f32s_async(float* L, const float* V, int64_t n, int64_t k, int64_t ldl,
+                              int sigma, void* ws, size_t ws_bytes, int64_t* d_info,
+                              cholmod_stream_t stream) {
+  return enqueue_f32s(L, V, n, k, ldl, sigma, ws, ws_bytes, d_info, (hipStream_t)stream);
+}
+
+int cholmod_update_f32s(float* L, const float* V, int64_t n, int64_t k, int64_t ldl, int sigma,
+                        cholmod_stream_t stream) {
+  int v = validate(L, V, n, k, ldl, sigma);
+  if (v) return v;
+  return run_sync(n, k, CHOLMOD_F32S, (hipStream_t)stream,
+                  [&](void* ws, size_t bytes, int64_t* d_info, hipStream_t st) {
+                    return enqueue_f32s(L, V, n, k, ldl, sigma, ws, bytes, d_info, st);
+                  });
+}
+
+size_t cholmod_workspace_bytes_batched(const cholmod_desc* descs, int64_t count) {
+  return batch_workspace_bytes(descs, count);
+}
+
+int cholmod_update_batched(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_bytes,
+                           int64_t* d_info, cholmod_stream_t stream) {
+  // every argument check happens here, before any HIP call
+  if (count < 0) return CHOLMOD_ERR_ARG;
+  if (count == 0) return CHOLMOD_OK;
+  const size_t tb = batch_table_bytes(descs, count);
+  const size_t need = batch_workspace_bytes(descs, count);
+  if (tb == 0 || need == 0) return CHOLMOD_ERR_ARG;
+  if (d_info == nullptr || ((uintptr_t)d_info & 7u) != 0) return CHOLMOD_ERR_ARG;
+  if (ws == nullptr || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return CHOLMOD_ERR_ARG;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return CHOLMOD_ERR_HIP;
   std::lock_guard<std::mutex> lk(g_mu);
   if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
   DevWs& d = g_ws[dev];
-  const size_t need = lay.total + kAlign;  // + info word
-  if (d.bytes < need) {
-    if (d.ptr) {
-      if (hipDeviceSynchronize() != hipSuccess) return CHOLMOD_ERR_HIP;
-      hipFree(d.ptr);
-      d.ptr = nullptr;
-      d.bytes = 0;
-    }
-    if (hipMalloc(&d.ptr, need) != hipSuccess) return CHOLMOD_ERR_HIP;
-    d.bytes = need;
+  // the pinned staging buffer is reused: wait for its previous upload
+  if (d.stage_pending) {
+    if (hipEventSynchronize(d.stage_done) != hipSuccess) return CHOLMOD_ERR_HIP;
+    d.stage_pending = false;
   }
-  if (!d.host_info) {
-    if (hipHostMalloc((void**)&d.host_info, sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
-      return CHOLMOD_ERR_HIP;
-  }
-  int64_t* d_info = (int64_t*)((char*)d.ptr + lay.total);
-  hipStream_t st = (hipStream_t)stream;
-  int rc = enqueue_f64(L, V, n, k, ldl, sigma, 0u, d.ptr, lay.total, d_info, st);
-  if (rc) return rc;
-  if (hipMemcpyAsync(d.host_info, d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st) !=
-      hipSuccess)
+  if (!d.stage_done && hipEventCreateWithFlags(&d.stage_done, hipEventDisableTiming) != hipSuccess)
     return CHOLMOD_ERR_HIP;
-  if (hipStreamSynchronize(st) != hipSuccess) return CHOLMOD_ERR_HIP;
-  return cholmod_decode_info(*d.host_info, k, nullptr, nullptr);
+  if (d.stage_bytes < tb) {
+    if (d.stage) hipHostFree(d.stage);
+    d.stage = nullptr;
+    d.stage_bytes = 0;
+    if (hipHostMalloc(&d.stage, tb, hipHostMallocDefault) != hipSuccess) return CHOLMOD_ERR_HIP;
+    d.stage_bytes = tb;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int rc = enqueue_batch(descs, count, ws, ws_bytes, d_info, st, d.stage, d.stage_bytes);
+  if (rc) return rc;
+  if (hipEventRecord(d.stage_done, st) != hipSuccess) return CHOLMOD_ERR_HIP;
+  d.stage_pending = true;
+  return CHOLMOD_OK;
 }
 
 }  // extern "C"

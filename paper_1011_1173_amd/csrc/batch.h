@@ -1,0 +1,39 @@
+// batch.h -- tables of the batched schedule, shared by the host planner
+// (api.hip) and the kernels (sysblk.hip).
+#pragma once
+#include <stdint.h>
+
+namespace chm {
+
+enum : int32_t { kStoreF64 = 0, kStoreF32 = 1 };
+
+// One factor of a batch, as the kernels see it (device table).
+struct BatchFactor {
+  void* L;         // caller's factor
+  const void* V;   // caller's V (read by the preparation launch only)
+  void* W;         // private copy of V in the workspace
+  void* T;         // rotation records, n x 16 slots of 32 bytes
+  int64_t* info;   // caller's info word for this factor
+  int64_t* stop;   // first failing row
+  int64_t n, k, ldl;
+  int32_t sigma, dtype;
+};
+
+// One factor's share of one step: block [pc, pc + bbc) of pass m0 (device
+// table; a step's entries are contiguous, longest factor first).
+struct BatchEntry {
+  int64_t pc, pa, m0;
+  int32_t f;       // factor index
+  int32_t bbc;     // rows of the block
+  int32_t kc;      // columns of V in this pass
+  int32_t rest0;   // index of the entry's first rest tile among the step's rest tiles
+};
+
+// Host-side description of one launch.
+struct BatchStep {
+  int64_t off;     // first entry
+  int64_t nent;    // entries (= chain workgroups)
+  int64_t nrest;   // rest tiles
+};
+
+}  // namespace chm

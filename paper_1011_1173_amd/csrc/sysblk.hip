@@ -20,27 +20,32 @@
 // a DPP row shift.  Column j of the block needs the rotations of all earlier
 // rows of the block before it becomes the diagonal:
 //   * rows r < j - 2 are applied by three helper waves, one lane per column
-//     j, in diagonal order: at step t the helper applies (r, m) with
+//     j, in diagonal order: at step t a helper applies (r, m) with
 //     r + m = t - 1, whose record wave 0 wrote to LDS at step t - 1; the
-//     waves split the columns of V 6 + 5 + 5 and hand the partly rotated
-//     L_rj on through LDS;
-//   * the helper leaves V_j after row j - 3 in LDS, and lane m of wave 0
-//     applies rows j - 2 and j - 1 itself at step j - 1 + m (the partly
-//     rotated L_rj moving from lane m to lane m+1), so V_j is ready for
-//     Compute(j, m) at the next step.
-// Inside the step loop nothing touches global memory except the report of
-// a failure.
+//     waves split the columns of V 6 + 5 + 5 and pass the partly rotated
+//     L_rj on through LDS.  After each rotation the helper publishes V_j[m]
+//     (by step parity); the value after row j - 3 is the hand-off;
+//   * lane m of wave 0 takes that hand-off and applies rows j - 2 and j - 1
+//     itself at step j - 1 + m (the partly rotated L_rj moving from lane m
+//     to lane m+1), so V_j is ready for Compute(j, m) at the next step.
+// The helpers never test whether a rotation is theirs: rows before the
+// block have identity records, and what they compute for rows >= j - 2 is
+// never read.  Wave 0 tests only while its pipeline fills and drains.  The
+// step loop touches no global memory; a failing Compute is remembered per
+// lane and reported after the loop.
 //
 // The apply tiles (head and rest).  A tile is 64 rows (the block) by 64
-// columns; 16 lanes per column, lane g applies rotation g of row s - g at
-// sub-step s, so the partly rotated L_rj moves to the next lane with a DPP
-// row shift while each lane keeps its V_j[g] in a register.
+// columns.  Lane g of a 16-lane group applies rotation g of row s - g at
+// sub-step s to four columns, so each record read from LDS serves four
+// columns; the partly rotated L_rj moves to lane g+1 with a DPP row shift
+// and each lane keeps its four V_j[g] in registers.
 //
 // Failures.  After a failure at row r the contents of rows >= r are
-// unspecified, so the kernels do not track the failure inside a block: a
-// failing Compute records (index, code) and the row with atomic minima, and
-// launches for later blocks (and later passes) skip the rows at or after it.
+// unspecified, so nothing inside a block depends on a failure: the first
+// failure is recorded with atomic minima (index/code, row), and launches
+// for later blocks and passes skip the rows at or after it.
 #include "rotations.h"
+#include "batch.h"
 
 namespace chm {
 
@@ -48,8 +53,9 @@ namespace {
 
 constexpr int kBR = 64;        // rows (and columns) of a block
 constexpr int kKP = 16;        // columns of V per pass
-constexpr int kCU = 2;         // rows wave 0 applies to the next column itself
-constexpr int kThreads = 1024;
+constexpr int kThreads = 256;  // 4 waves
+constexpr int kPad = 16;       // identity record rows before the block
+constexpr int kRRows = kPad + kBR + kKP;  // record rows -16 .. 79
 
 // Rotation record of this schedule: the Apply operands of (row, column m).
 struct alignas(32) RotRec {
@@ -60,17 +66,32 @@ struct alignas(32) RotRec {
 };
 static_assert(sizeof(RotRec) == sizeof(Coef), "record size");
 
+// Record as stored in the workspace between launches, in the storage type.
+template <typename ST>
+struct alignas(4 * sizeof(ST)) GRec {
+  ST c, s, ic, ss;
+};
+
 // Original diagonal of a row, with the values its first Compute starts from.
 struct DiagPre {
   double l, t, il, pad;  // L_ii, L_ii * L_ii, 1 / L_ii
 };
 
+// What wave 0 produces at its step of row i: L(i-1, i+1), L(i, i+1), L(i, i).
+struct Band {
+  double lo, hi, d, pad;
+};
+
 struct SbLds {
-  double Lb[kBR][kBR + 1];  // the block's upper triangle (original, then final)
-  double A[kBR][kBR + 1];   // apply tile: rows of block b-1 x 64 columns
-  RotRec R[kBR][kKP];       // records of block b-1 (apply), then of block b
-  double H[kBR][kKP + 1];   // V of the block's columns: head result, then hand-off
+  double Lb[kBR][kBR + 1];  // the block's original upper triangle
+  union {
+    double A[kBR][kBR + 4];      // apply tile: rows of block b-1 x 64 columns
+    double Lh[kPad + kBR][kBR];  // helper results after the last rotation, rows -16..63
+  };
+  RotRec R[kRRows][kKP];    // records by row + 16: identity / block rows / identity
+  double Hb[kKP][2][kBR];   // V_j[m] after each helper rotation, by step parity
   double X[2][2][kBR];      // helper h -> h+1, by step parity
+  Band Lc[kRRows];          // wave 0 results by row + 16
   DiagPre dg[kBR];
   int64_t lim;              // first failing row known at launch
 };
@@ -84,57 +105,101 @@ __device__ __forceinline__ double sb_shr1(double x, double fill) {
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-__device__ __forceinline__ int clamp_row(int r) { return r < 0 ? 0 : (r > kBR - 1 ? kBR - 1 : r); }
+__device__ __forceinline__ float sb_shr1(float x, float fill) {
+  const int b = __builtin_bit_cast(int, x), f = __builtin_bit_cast(int, fill);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(f, b, 0x111, 0xF, 0xF, false));
+}
 
-// Apply the records of rows [pa, pa + rows) to columns [j0, j0 + ncols).
-// HEAD: V of those columns stays in sh.H; otherwise it goes back to W.
-template <bool HEAD>
-__device__ __forceinline__ void apply_tile(SbLds& sh, double* __restrict__ L, int64_t ldl,
-                                           double* __restrict__ W, int64_t ldw, int kc,
-                                           int64_t pa, int rows, int64_t j0, int ncols,
-                                           const RotRec* __restrict__ T) {
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+
+__device__ __forceinline__ RotRec identity_rec() {
+  RotRec r;
+  r.c = 1.0; r.s = 0.0; r.ic = 1.0; r.ss = 0.0;
+  return r;
+}
+
+// sh.R <- identity records, except the records of rows [p, p + rows)
+// (columns m < kc) at row offset kPad.
+template <typename ST>
+__device__ __forceinline__ void load_records(SbLds& sh, const GRec<ST>* __restrict__ T, int64_t p,
+                                             int rows, int kc) {
+  for (int idx = threadIdx.x; idx < kRRows * kKP; idx += kThreads) {
+    const int rr = idx >> 4, m = idx & 15, r = rr - kPad;
+    RotRec rec = identity_rec();
+    if (r >= 0 && r < rows && m < kc) {
+      const GRec<ST> g = T[(p + r) * kKP + m];
+      rec.c = g.c; rec.s = g.s; rec.ic = g.ic; rec.ss = g.ss;
+    }
+    sh.R[rr][m] = rec;
+  }
+}
+
+// Apply the records in sh.R (rows [pa, pa + 64)) to columns [j0, j0 + ncols).
+// HEAD: V of those columns goes to sh.Hb parity 1 (the chain's initial
+// values); otherwise back to W.  The caller has filled sh.R.  The arithmetic
+// runs in the storage type ST (the records hold ST values).
+template <bool HEAD, int SG, typename ST>
+__device__ __forceinline__ void apply_tile(SbLds& sh, ST* __restrict__ L, int64_t ldl,
+                                           ST* __restrict__ W, int64_t ldw, int kc,
+                                           int64_t pa, int64_t j0, int ncols) {
   const int tid = threadIdx.x;
-  const int c = tid >> 4, g = tid & 15;
-  double a[4];
+  const int g = tid & 15, grp = tid >> 4;  // lane g of group grp: columns grp + 16 q
+  for (int idx = tid; idx < kBR * kBR; idx += kThreads) {
+    const int r = idx >> 6, c = idx & 63;
+    sh.A[r][c] = c < ncols ? (double)L[(pa + r) * ldl + j0 + c] : 0.0;
+  }
+  ST w[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int idx = tid + q * kThreads, r = idx >> 6, cc = idx & 63;
-    a[q] = (r < rows && cc < ncols) ? L[(pa + r) * ldl + j0 + cc] : 0.0;
+    const int c = grp + 16 * q;
+    w[q] = (c < ncols && g < kc) ? W[(j0 + c) * ldw + g] : (ST)0;
   }
-  RotRec rec;
-  rec.c = 1.0; rec.s = 0.0; rec.ic = 1.0; rec.ss = 0.0;
-  if (c < rows && g < kc) rec = T[(pa + c) * kKP + g];
-  double w = (c < ncols && g < kc) ? W[(j0 + c) * ldw + g] : 0.0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int idx = tid + q * kThreads;
-    sh.A[idx >> 6][idx & 63] = a[q];
-  }
-  sh.R[c][g] = rec;
   __syncthreads();
-  double xs = 0.0;
-  const int S = rows + kc - 1;
+  ST xs[4] = {0, 0, 0, 0};
+  const int S = kBR + kc - 1;
   for (int s = 0; s < S; ++s) {
     const int r = s - g;
-    const bool act = (g < kc) && (r >= 0) && (r < rows);
-    const double xin = (g == 0) ? sh.A[clamp_row(s)][c] : xs;
-    const RotRec cf = sh.R[clamp_row(r)][g];
-    const double x = __builtin_fma(cf.ss, w, xin) * cf.ic;
-    const double wn = __builtin_fma(-cf.s, x, cf.c * w);
-    w = act ? wn : w;
-    if (act && g == kc - 1) sh.A[r][c] = x;
-    xs = sb_shr1(x, 0.0);
+    ST xin[4];
+    if (g == 0) {
+      const int rs = imin(s, kBR - 1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xin[q] = (ST)sh.A[rs][grp + 16 * q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xin[q] = xs[q];
+    }
+    const RotRec& cf = sh.R[imin(r, kBR + kKP - 1) + kPad][g];  // r >= -15
+    const ST c = (ST)cf.c, sn = (ST)cf.s, ic = (ST)cf.ic;
+    ST x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      x[q] = fma_t((ST)SG * sn, w[q], xin[q]) * ic;
+      w[q] = fma_t(-sn, x[q], c * w[q]);
+    }
+    if (g == kc - 1 && r >= 0 && r < kBR) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sh.A[r][grp + 16 * q] = x[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xs[q] = sb_shr1(x[q], (ST)0);
   }
   __syncthreads();
+  for (int idx = tid; idx < kBR * kBR; idx += kThreads) {
+    const int r = idx >> 6, c = idx & 63;
+    if (c < ncols) L[(pa + r) * ldl + j0 + c] = (ST)sh.A[r][c];
+  }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int idx = tid + q * kThreads, r = idx >> 6, cc = idx & 63;
-    if (r < rows && cc < ncols) L[(pa + r) * ldl + j0 + cc] = sh.A[r][cc];
-  }
-  if (HEAD) {
-    if (g < kc) sh.H[c][g] = w;
-  } else {
-    if (c < ncols && g < kc) W[(j0 + c) * ldw + g] = w;
+    const int c = grp + 16 * q;
+    if (HEAD) {
+      if (g < kc) sh.Hb[g][1][c] = (double)w[q];
+    } else {
+      if (c < ncols && g < kc) W[(j0 + c) * ldw + g] = w[q];
+    }
   }
 }
 
@@ -144,178 +209,190 @@ __device__ __forceinline__ void apply_tile(SbLds& sh, double* __restrict__ L, in
 constexpr int kSt = 13;
 
 // Wave 0 layout: st[0] radicand and st[1] 1/L_ii from lane m-1, st[2] L_ii
-// of the next row (lane 0), st[3] V_i[m] for this step's Compute,
-// st[4 .. 4+kCU) L_{r, i+1} for rows i-kCU+1..i rotated through columns < m,
-// st[4+kCU .. 8+kCU) this lane's record of row i-1.
-constexpr int kCsLf = 4, kCsPrev = 4 + kCU;
-static_assert(kCU == 2, "wave 0 keeps one earlier record");
-static_assert(kCsPrev + 4 <= kSt, "state size");
-
+// of the next row (used by lane 0), st[3] V_i[m] for this step's Compute,
+// st[4], st[5] L(i-1, i+1) and L(i, i+1) rotated through columns < m,
+// st[6..8] this lane's record {c, s, 1/c} of row i-1.
 __device__ __forceinline__ void chain_init(SbLds& sh, double (&st)[kSt], int lane, int bbc) {
   const DiagPre d0 = sh.dg[0];
   st[0] = d0.t;
   st[1] = d0.il;
   st[2] = d0.l;
-  st[3] = sh.H[0][lane & 15];
+  st[3] = sh.Hb[lane & 15][1][0];
+  st[4] = 0.0;
+  st[5] = (lane == 0 && bbc > 1) ? sh.Lb[0][1] : 0.0;
+  st[6] = 1.0;
+  st[7] = 0.0;
+  st[8] = 1.0;
 #pragma unroll
-  for (int q = 0; q < kCU; ++q) {
-    const int r = 1 - kCU + q;
-    st[kCsLf + q] = (lane == 0 && r >= 0 && bbc > 1) ? sh.Lb[r < 0 ? 0 : r][1] : 0.0;
-  }
-  st[kCsPrev + 0] = 1.0;  // c
-  st[kCsPrev + 1] = 0.0;  // s
-  st[kCsPrev + 2] = 1.0;  // ic
-  st[kCsPrev + 3] = 0.0;  // ss
-  for (int u = kCsPrev + 4; u < kSt; ++u) st[u] = 0.0;
+  for (int u = 9; u < kSt; ++u) st[u] = 0.0;
 }
 
-__device__ __forceinline__ void chain_step(SbLds& sh, double (&st)[kSt], int t, int m, int kc,
-                                           int bbc, double sg, int64_t pc, int64_t kfull,
-                                           int64_t m0, int64_t* __restrict__ info,
-                                           int64_t* __restrict__ stop_row) {
+// One step of wave 0, lanes m < kc.  CHECK: the pipeline is filling or
+// draining (some lane has i < 0, or i + 1 >= bbc).
+template <bool CHECK, int SG>
+__device__ __forceinline__ void chain_step(SbLds& sh, double (&st)[kSt], int& fkey, int t, int m,
+                                           int bbc) {
   const int i = t - m;
-  const bool cval = (m < kc) && (i >= 0) && (i < bbc);
   const int jj = i + 1;
-  const bool jval = (m < kc) && (jj >= 1) && (jj < bbc);
-  // LDS reads: the hand-off of column jj, lane 0's inputs of the next step
-  double Wc = sh.H[clamp_row(jj)][m & 15];
-  const DiagPre dn = sh.dg[clamp_row(t + 1)];
-  double fill[kCU];
-#pragma unroll
-  for (int q = 0; q < kCU; ++q) {
-    const int r = t + 2 - kCU + q, col = t + 2;
-    const double f = sh.Lb[clamp_row(r)][clamp_row(col)];
-    fill[q] = (r >= 0 && col < bbc) ? f : 0.0;
-  }
+  double Wc = sh.Hb[m][(t - 1) & 1][jj & 63];
+  const DiagPre dn = sh.dg[imin(t + 1, kBR - 1)];
+  const int cn = imin(t + 2, kBR - 1);
+  const double f0 = sh.Lb[imin(t, kBR - 1)][cn];
+  const double f1 = sh.Lb[imin(t + 1, kBR - 1)][cn];
   // Compute(i, m)
   const double tpi = st[0], ili = st[1];
   const double lin = (m == 0) ? st[2] : tpi * ili;
   const double v = st[3];
-  const double tt = __builtin_fma(sg * v, v, tpi);
+  const double tt = __builtin_fma(SG * v, v, tpi);
   const double y = rsqrt_refined(tt);
   const double ww = tt * y;
-  const bool bad = (m == 0) && !(lin > 0.0);
-  const bool npd = !bad && !(tt > 0.0);
-  const bool ok = cval && !bad && !npd;
-  RotRec cur;
   const double s = v * ili;
-  cur.c = ok ? ww * ili : 1.0;
-  cur.s = ok ? s : 0.0;
-  cur.ic = ok ? lin * y : 1.0;
-  cur.ss = ok ? sg * s : 0.0;
-  const double t_out = ok ? tt : tpi, y_out = ok ? y : ili;
-  if (cval && !ok) {
-    const int64_t code = bad ? kCodeBadDiag : kCodeNotPD;
-    atomicMin((unsigned long long*)info,
-              (unsigned long long)info_key((pc + i) * kfull + m0 + m, code));
-    atomicMin((unsigned long long*)stop_row, (unsigned long long)(pc + i));
-  }
-  if (cval) sh.R[i][m] = cur;
-  if (ok && m == kc - 1) sh.Lb[i][i] = ww;
+  const double c = ww * ili;
+  const double ic = lin * y;
+  const bool valid = !CHECK || (i >= 0 && i < bbc);
+  const int code =
+      (m == 0 && !(lin > 0.0)) ? (int)kCodeBadDiag : (!(tt > 0.0) ? (int)kCodeNotPD : 0);
+  if (valid && code != 0) fkey = imin(fkey, (i << 2) | code);
+  RotRec cur;
+  cur.c = c; cur.s = s; cur.ic = ic; cur.ss = SG * s;
+  sh.R[CHECK ? (valid ? i + kPad : kRRows - 1) : i + kPad][m] = cur;
   // rows i-1 (record of the previous step) and i applied to column jj
-  RotRec prev;
-  prev.c = st[kCsPrev + 0];
-  prev.s = st[kCsPrev + 1];
-  prev.ic = st[kCsPrev + 2];
-  prev.ss = st[kCsPrev + 3];
-  double Lo[kCU];
-#pragma unroll
-  for (int q = 0; q < kCU; ++q) {
-    const int r = i - kCU + 1 + q;
-    const RotRec cf = (q == kCU - 1) ? cur : prev;
-    const bool rv = jval && (r >= 0);
-    const double x = __builtin_fma(cf.ss, Wc, st[kCsLf + q]) * cf.ic;
-    const double wn = __builtin_fma(-cf.s, x, cf.c * Wc);
-    Wc = rv ? wn : Wc;
-    Lo[q] = rv ? x : st[kCsLf + q];
-    if (rv && m == kc - 1) sh.Lb[r][jj] = x;
+  const double pc = st[6], ps = st[7], pic = st[8];
+  const double x0 = __builtin_fma(SG * ps, Wc, st[4]) * pic;
+  Wc = __builtin_fma(-ps, x0, pc * Wc);
+  const double x1 = __builtin_fma(SG * s, Wc, st[5]) * ic;
+  Wc = __builtin_fma(-s, x1, c * Wc);
+  Band b;
+  b.lo = x0; b.hi = x1; b.d = ww; b.pad = 0.0;
+  sh.Lc[CHECK ? imax(imin(i + kPad, kRRows - 1), 0) : i + kPad] = b;
+  if (CHECK) {
+    const bool started = i >= 0;
+    st[3] = started ? Wc : st[3];
+    st[6] = started ? c : 1.0;
+    st[7] = started ? s : 0.0;
+    st[8] = started ? ic : 1.0;
+  } else {
+    st[3] = Wc;
+    st[6] = c;
+    st[7] = s;
+    st[8] = ic;
   }
-  if (jval) st[3] = Wc;
-  st[kCsPrev + 0] = cur.c;
-  st[kCsPrev + 1] = cur.s;
-  st[kCsPrev + 2] = cur.ic;
-  st[kCsPrev + 3] = cur.ss;
   // to lane m+1 (lane 0 takes row t+1's originals)
-#pragma unroll
-  for (int q = 0; q < kCU; ++q) st[kCsLf + q] = sb_shr1(Lo[q], fill[q]);
-  st[0] = sb_shr1(t_out, dn.t);
-  st[1] = sb_shr1(y_out, dn.il);
+  st[4] = sb_shr1(x0, f0);
+  st[5] = sb_shr1(x1, f1);
+  st[0] = sb_shr1(tt, dn.t);
+  st[1] = sb_shr1(y, dn.il);
   st[2] = dn.l;
 }
 
 // Helper wave layout (columns [MLO, MLO + CNT) of V, lane jj = block column):
 // st[u] V_jj[MLO+u] after the rows applied so far, st[CNT+u] L_{r, jj} after
-// rotation MLO+u (for the next step), st[2*CNT] the original L_{t, jj}
-// (first helper).
+// rotation MLO+u (input of the next step), st[2*CNT] the original L_{t, jj}
+// (first helper only).
 template <int MLO, int CNT>
 __device__ __forceinline__ void helper_init(SbLds& sh, double (&st)[kSt], int jj) {
   static_assert(2 * CNT + 1 <= kSt, "state size");
 #pragma unroll
   for (int u = 0; u < kSt; ++u) st[u] = 0.0;
 #pragma unroll
-  for (int u = 0; u < CNT; ++u) st[u] = sh.H[jj][MLO + u];
+  for (int u = 0; u < CNT; ++u) st[u] = sh.Hb[MLO + u][1][jj];
   st[2 * CNT] = sh.Lb[0][jj];
 }
 
-template <int H, int MLO, int CNT>
-__device__ __forceinline__ void helper_step(SbLds& sh, double (&st)[kSt], int t, int jj, int kc,
-                                            int bbc) {
-  RotRec cf[CNT];
+template <int H, int MLO, int CNT, int SG>
+__device__ __forceinline__ void helper_step(SbLds& sh, double (&st)[kSt], int t, int jj, int kc) {
+  double c[CNT], sn[CNT], ic[CNT];
 #pragma unroll
-  for (int u = 0; u < CNT; ++u) cf[u] = sh.R[clamp_row(t - 1 - MLO - u)][MLO + u];
+  for (int u = 0; u < CNT; ++u) {
+    const int rr = imin(t - 1 - MLO - u + kPad, kRRows - 1);  // >= 0: t >= 0, MLO + u < 16
+    const RotRec& cf = sh.R[rr][MLO + u];
+    c[u] = cf.c;
+    sn[u] = cf.s;
+    ic[u] = cf.ic;
+  }
   const double xin0 = (H == 0) ? st[2 * CNT] : sh.X[H > 0 ? H - 1 : 0][(t - 1) & 1][jj];
   double Lold[CNT];
 #pragma unroll
   for (int u = 0; u < CNT; ++u) Lold[u] = st[CNT + u];
 #pragma unroll
   for (int u = 0; u < CNT; ++u) {
-    const int m = MLO + u, r = t - 1 - m;
-    const bool act = (m < kc) && (r >= 0) && (r < jj - kCU) && (jj < bbc);
-    const double lin = (u == 0) ? xin0 : Lold[u > 0 ? u - 1 : 0];
-    const double x = __builtin_fma(cf[u].ss, st[u], lin) * cf[u].ic;
-    const double wn = __builtin_fma(-cf[u].s, x, cf[u].c * st[u]);
-    st[u] = act ? wn : st[u];
-    st[CNT + u] = x;
-    if (act && m == kc - 1) sh.Lb[r][jj] = x;
-    if (act && r == jj - kCU - 1) sh.H[jj][m] = wn;
+    const int m = MLO + u;
+    if (m < kc) {
+      const double lin = (u == 0) ? xin0 : Lold[u > 0 ? u - 1 : 0];
+      const double x = __builtin_fma(SG * sn[u], st[u], lin) * ic[u];
+      st[u] = __builtin_fma(-sn[u], x, c[u] * st[u]);
+      st[CNT + u] = x;
+      sh.Hb[m][t & 1][jj] = st[u];
+      if (m == kc - 1) sh.Lh[imin(t - 1 - m + kPad, kPad + kBR - 1)][jj] = x;
+    }
   }
   if (H < 2) sh.X[H < 2 ? H : 0][t & 1][jj] = st[2 * CNT - 1];
-  if (H == 0) st[2 * CNT] = sh.Lb[clamp_row(t)][jj];
+  if (H == 0) st[2 * CNT] = sh.Lb[imin(t, kBR - 1)][jj];
+}
+
+// Each role runs its own step loop; every loop passes the same number of
+// barriers, one per step (the role is wave-uniform, so no wave enters
+// another role's loop).
+template <bool CHECK, int SG>
+__device__ __forceinline__ void chain_steps(SbLds& sh, double (&st)[kSt], int& fkey, int t0,
+                                            int t1, int lane, int kc, int bbc) {
+  for (int t = t0; t < t1; ++t) {
+    if (lane < kc) chain_step<CHECK, SG>(sh, st, fkey, t, lane, bbc);
+    __syncthreads();
+  }
+}
+
+template <int H, int MLO, int CNT, int SG>
+__device__ __forceinline__ void helper_steps(SbLds& sh, int nsteps, int lane, int kc) {
+  double st[kSt];
+  helper_init<MLO, CNT>(sh, st, lane);
+  __syncthreads();
+  for (int t = 0; t < nsteps; ++t) {
+    helper_step<H, MLO, CNT, SG>(sh, st, t, lane, kc);
+    __syncthreads();
+  }
 }
 
 // Workgroup 0: head tile, then the chain of block [pc, pc + bbc).
-__device__ __forceinline__ void chain_wg(SbLds& sh, double* __restrict__ L, int64_t ldl,
-                                         double* __restrict__ W, int64_t ldw, int kc,
-                                         int64_t kfull, int64_t m0, double sg, int64_t pc,
-                                         int bbc, int64_t pa, RotRec* __restrict__ T,
+template <int SG, typename ST>
+__device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t ldl,
+                                         ST* __restrict__ W, int64_t ldw, int kc,
+                                         int64_t kfull, int64_t m0, int64_t pc, int bbc,
+                                         int64_t pa, GRec<ST>* __restrict__ T,
                                          int64_t* __restrict__ info,
                                          int64_t* __restrict__ stop_row, int64_t lim) {
   const int tid = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const bool head = pa >= 0 && pa < lim;
+  if (head) {
+    load_records(sh, T, pa, lim - pa < kBR ? (int)(lim - pa) : kBR, kc);
+  } else {
+    for (int idx = tid; idx < kRRows * kKP; idx += kThreads)
+      sh.R[idx >> 4][idx & 15] = identity_rec();
+  }
   if (pc >= lim) {
     // a failure in block b-1: finish its rows before the failure, nothing else
-    if (head) apply_tile<true>(sh, L, ldl, W, ldw, kc, pa, (int)(lim - pa), pc, bbc, T);
+    if (head) apply_tile<true, SG, ST>(sh, L, ldl, W, ldw, kc, pa, pc, bbc);
     return;
   }
-  double lt[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int idx = tid + q * kThreads, i = idx >> 6, j = idx & 63;
-    lt[q] = (i < bbc && j < bbc && j >= i) ? L[(pc + i) * ldl + pc + j] : 0.0;
+  for (int idx = tid; idx < kBR * kBR; idx += kThreads) {
+    const int i = idx >> 6, j = idx & 63;
+    sh.Lb[i][j] = (i < bbc && j < bbc && j >= i) ? (double)L[(pc + i) * ldl + pc + j] : 0.0;
   }
   if (head) {
-    const int rows = lim - pa < kBR ? (int)(lim - pa) : kBR;
-    apply_tile<true>(sh, L, ldl, W, ldw, kc, pa, rows, pc, bbc, T);
+    apply_tile<true, SG, ST>(sh, L, ldl, W, ldw, kc, pa, pc, bbc);
   } else {
-    const int c = tid >> 4, g = tid & 15;
-    if (g < kc) sh.H[c][g] = c < bbc ? W[(pc + c) * ldw + g] : 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int idx = tid + q * kThreads;
-    sh.Lb[idx >> 6][idx & 63] = lt[q];
+    for (int idx = tid; idx < kBR * kKP; idx += kThreads) {
+      const int c = idx >> 4, g = idx & 15;
+      if (g < kc) sh.Hb[g][1][c] = c < bbc ? (double)W[(pc + c) * ldw + g] : 0.0;
+    }
   }
   __syncthreads();
+  // identity records for this block's rows until wave 0 writes them
+  for (int idx = tid; idx < kRRows * kKP; idx += kThreads) {
+    if ((idx >> 4) >= kPad) sh.R[idx >> 4][idx & 15] = identity_rec();
+  }
+  for (int idx = tid; idx < 2 * kBR; idx += kThreads) sh.X[idx >> 6][1][idx & 63] = 0.0;
   if (tid < kBR) {
     const double l = sh.Lb[tid][tid];
     DiagPre d;
@@ -326,80 +403,205 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, double* __restrict__ L, int6
     sh.dg[tid] = d;
   }
   __syncthreads();
-  if (tid >= 256) return;  // the chain uses waves 0..3; barriers count live waves only
-  const int wv = tid >> 6, lane = tid & 63;
-  double st[kSt];
-  if (wv == 0) chain_init(sh, st, lane, bbc);
-  else if (wv == 1) helper_init<0, 6>(sh, st, lane);
-  else if (wv == 2) helper_init<6, 5>(sh, st, lane);
-  else helper_init<11, 5>(sh, st, lane);
-  __syncthreads();
+  // steady steps [s0, s1): every lane m < kc has i >= 0 and i + 1 < bbc
   const int nsteps = bbc + kc - 1;
-  for (int t0 = 0; t0 < nsteps; t0 += 2) {
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int t = t0 + u;
-      if (t < nsteps) {
-        if (wv == 0) chain_step(sh, st, t, lane, kc, bbc, sg, pc, kfull, m0, info, stop_row);
-        else if (wv == 1) helper_step<0, 0, 6>(sh, st, t, lane, kc, bbc);
-        else if (wv == 2) helper_step<1, 6, 5>(sh, st, t, lane, kc, bbc);
-        else helper_step<2, 11, 5>(sh, st, t, lane, kc, bbc);
-      }
-      __syncthreads();
+  const int s0 = kc - 1, s1 = imax(kc - 1, bbc - 1);
+  if (wv == 0) {
+    double st[kSt];
+    int fkey = 0x7fffffff;
+    chain_init(sh, st, lane, bbc);
+    __syncthreads();
+    chain_steps<true, SG>(sh, st, fkey, 0, s0, lane, kc, bbc);
+    chain_steps<false, SG>(sh, st, fkey, s0, s1, lane, kc, bbc);
+    chain_steps<true, SG>(sh, st, fkey, s1, nsteps, lane, kc, bbc);
+    if (lane < kc && fkey != 0x7fffffff) {
+      const int64_t i = fkey >> 2, code = fkey & 3;
+      atomicMin((unsigned long long*)info,
+                (unsigned long long)info_key((pc + i) * kfull + m0 + lane, code));
+      atomicMin((unsigned long long*)stop_row, (unsigned long long)(pc + i));
+    }
+  } else if (wv == 1) {
+    helper_steps<0, 0, 6, SG>(sh, nsteps, lane, kc);
+  } else if (wv == 2) {
+    helper_steps<1, 6, 5, SG>(sh, nsteps, lane, kc);
+  } else {
+    helper_steps<2, 11, 5, SG>(sh, nsteps, lane, kc);
+  }
+  // the block's triangle (diagonal and two superdiagonals from wave 0, the
+  // rest from the helper holding column kc - 1 of V) and its records
+  for (int idx = tid; idx < kBR * kBR; idx += kThreads) {
+    const int i = idx >> 6, j = idx & 63;
+    if (i < bbc && j < bbc && j >= i) {
+      double x;
+      if (j == i) x = sh.Lc[i + kPad].d;
+      else if (j == i + 1) x = sh.Lc[i + kPad].hi;
+      else if (j == i + 2) x = sh.Lc[i + 1 + kPad].lo;
+      else x = sh.Lh[i + kPad][j];
+      L[(pc + i) * ldl + pc + j] = (ST)x;
     }
   }
-  // the block's triangle and its records
-  for (int idx = tid; idx < kBR * kBR; idx += 256) {
-    const int i = idx >> 6, j = idx & 63;
-    if (i < bbc && j < bbc && j >= i) L[(pc + i) * ldl + pc + j] = sh.Lb[i][j];
-  }
-  for (int idx = tid; idx < kBR * kKP; idx += 256) {
+  for (int idx = tid; idx < kBR * kKP; idx += kThreads) {
     const int r = idx >> 4, m = idx & 15;
-    if (r < bbc && m < kc) T[(pc + r) * kKP + m] = sh.R[r][m];
+    if (r < bbc && m < kc) {
+      const RotRec& rec = sh.R[r + kPad][m];
+      GRec<ST> g;
+      g.c = (ST)rec.c; g.s = (ST)rec.s; g.ic = (ST)rec.ic; g.ss = (ST)rec.ss;
+      T[(pc + r) * kKP + m] = g;
+    }
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_sb_block(
-    double* __restrict__ L, int64_t ldl, double* __restrict__ W, int64_t ldw, int kc,
-    int64_t kfull, int64_t m0, double sg, int64_t n, int64_t pc, int bbc, int64_t pa,
-    RotRec* __restrict__ T, int64_t* __restrict__ info, int64_t* __restrict__ stop_row) {
-  __shared__ SbLds sh;
+// One workgroup's share of the launch for block [pc, pc + bbc) of one factor:
+// wg == 0 runs the chain, wg >= 1 applies block [pa, pa + 64) to the
+// 64-column tile wg - 1 right of the block.
+template <int SG, typename ST>
+__device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_t ldl,
+                                           ST* __restrict__ W, int64_t ldw, int kc,
+                                           int64_t kfull, int64_t m0, int64_t n, int64_t pc,
+                                           int bbc, int64_t pa, GRec<ST>* __restrict__ T,
+                                           int64_t* __restrict__ info,
+                                           int64_t* __restrict__ stop_row, int wg) {
   // one read of the failure row per workgroup, so that every wave takes the same path
   if (threadIdx.x == 0)
     sh.lim = __hip_atomic_load(stop_row, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   const int64_t lim = sh.lim;
-  if (blockIdx.x == 0) {
-    chain_wg(sh, L, ldl, W, ldw, kc, kfull, m0, sg, pc, bbc, pa, T, info, stop_row, lim);
+  if (wg == 0) {
+    chain_wg<SG, ST>(sh, L, ldl, W, ldw, kc, kfull, m0, pc, bbc, pa, T, info, stop_row, lim);
   } else {
     if (pa < 0 || pa >= lim) return;
-    const int64_t j0 = pc + bbc + (int64_t)(blockIdx.x - 1) * kBR;
-    const int rows = lim - pa < kBR ? (int)(lim - pa) : kBR;
+    const int64_t j0 = pc + bbc + (int64_t)(wg - 1) * kBR;
     const int ncols = n - j0 < kBR ? (int)(n - j0) : kBR;
-    apply_tile<false>(sh, L, ldl, W, ldw, kc, pa, rows, j0, ncols, T);
+    load_records(sh, T, pa, lim - pa < kBR ? (int)(lim - pa) : kBR, kc);
+    apply_tile<false, SG, ST>(sh, L, ldl, W, ldw, kc, pa, j0, ncols);
   }
 }
 
-}  // namespace
+template <int SG, typename ST>
+__global__ __launch_bounds__(kThreads) void k_sb_block(
+    ST* __restrict__ L, int64_t ldl, ST* __restrict__ W, int64_t ldw, int kc, int64_t kfull,
+    int64_t m0, int64_t n, int64_t pc, int bbc, int64_t pa, GRec<ST>* __restrict__ T,
+    int64_t* __restrict__ info, int64_t* __restrict__ stop_row) {
+  __shared__ SbLds sh;
+  block_work<SG, ST>(sh, L, ldl, W, ldw, kc, kfull, m0, n, pc, bbc, pa, T, info, stop_row,
+                     (int)blockIdx.x);
+}
 
-// Fast blocked schedule: V columns in passes of 16, one launch per block of
-// 64 rows.  W is the private copy of V (row stride k); T holds n x 16 records.
-hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
-                      double sg, Coef* T, int64_t* info, int64_t* stop, double* /*sink*/) {
-  RotRec* R = reinterpret_cast<RotRec*>(T);
+// Batched form: the launch of step s holds, for every factor with more than
+// s steps, the chain workgroup of its step s (workgroups [0, nent), longest
+// factor first) and then all their rest tiles.
+__global__ __launch_bounds__(kThreads) void k_sb_batch(const BatchFactor* __restrict__ fac,
+                                                       const BatchEntry* __restrict__ ent,
+                                                       int nent) {
+  __shared__ SbLds sh;
+  const int x = (int)blockIdx.x;
+  int e = x, wg = 0;
+  if (x >= nent) {
+    const int r = x - nent;  // rest tile r of the step: largest e with ent[e].rest0 <= r
+    int lo = 0, hi = nent - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ent[mid].rest0 <= r) lo = mid;
+      else hi = mid - 1;
+    }
+    e = lo;
+    wg = 1 + r - ent[lo].rest0;
+  }
+  const BatchEntry E = ent[e];
+  const BatchFactor F = fac[E.f];
+  if (F.dtype == kStoreF64) {
+    double* L = (double*)F.L;
+    double* W = (double*)F.W + E.m0;
+    GRec<double>* T = (GRec<double>*)F.T;
+    if (F.sigma > 0)
+      block_work<1, double>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+                            F.info, F.stop, wg);
+    else
+      block_work<-1, double>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+                             F.info, F.stop, wg);
+  } else {
+    float* L = (float*)F.L;
+    float* W = (float*)F.W + E.m0;
+    GRec<float>* T = (GRec<float>*)F.T;
+    if (F.sigma > 0)
+      block_work<1, float>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+                           F.info, F.stop, wg);
+    else
+      block_work<-1, float>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+                            F.info, F.stop, wg);
+  }
+}
+
+// Batched preparation: W <- V for every factor, info and stop row reset.
+// Grid (chunks, factors).
+__global__ void k_prepare_batch(const BatchFactor* __restrict__ fac) {
+  const BatchFactor F = fac[blockIdx.y];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *F.info = INT64_MAX;
+    *F.stop = INT64_MAX;
+  }
+  const int64_t words = F.n * F.k * (F.dtype == kStoreF64 ? 2 : 1);  // 4-byte words
+  const uint32_t* __restrict__ src = (const uint32_t*)F.V;
+  uint32_t* __restrict__ dst = (uint32_t*)F.W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+    dst[i] = src[i];
+}
+
+template <typename ST>
+hipError_t run_sysblk_t(hipStream_t st, ST* L, int64_t n, int64_t ldl, ST* W, int64_t k, int sg,
+                        void* Tws, int64_t* info, int64_t* stop) {
+  GRec<ST>* R = reinterpret_cast<GRec<ST>*>(Tws);
   for (int64_t m0 = 0; m0 < k; m0 += kKP) {
     const int kc = (int)((k - m0) < kKP ? (k - m0) : kKP);
-    double* Wc = W + m0;
+    ST* Wc = W + m0;
     for (int64_t pc = 0; pc < n; pc += kBR) {
       const int bbc = (int)((n - pc) < kBR ? (n - pc) : kBR);
       const int64_t pa = pc - kBR;  // previous block (always full), or < 0
       const int64_t rest = n - (pc + bbc);
       const unsigned grid = 1u + (pa >= 0 ? (unsigned)((rest + kBR - 1) / kBR) : 0u);
-      hipLaunchKernelGGL(k_sb_block, dim3(grid), dim3(kThreads), 0, st, L, ldl, Wc, k, kc, k, m0,
-                         sg, n, pc, bbc, pa, R, info, stop);
+      if (sg > 0)
+        hipLaunchKernelGGL((k_sb_block<1, ST>), dim3(grid), dim3(kThreads), 0, st, L, ldl, Wc, k,
+                           kc, k, m0, n, pc, bbc, pa, R, info, stop);
+      else
+        hipLaunchKernelGGL((k_sb_block<-1, ST>), dim3(grid), dim3(kThreads), 0, st, L, ldl, Wc,
+                           k, kc, k, m0, n, pc, bbc, pa, R, info, stop);
     }
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+// Batched launches: one preparation launch, then one launch per step.
+hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
+                            const BatchEntry* d_ent, const BatchStep* steps, int64_t nsteps) {
+  if (count > 0) {
+    const unsigned fy = (unsigned)count;
+    hipLaunchKernelGGL(k_prepare_batch, dim3(8, fy), dim3(256), 0, st, d_fac);
+  }
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const BatchStep& S = steps[s];
+    if (S.nent == 0) continue;
+    hipLaunchKernelGGL(k_sb_batch, dim3((unsigned)(S.nent + S.nrest)), dim3(kThreads), 0, st,
+                       d_fac, d_ent + S.off, (int)S.nent);
+  }
+  return hipGetLastError();
+}
+
+// Fast blocked schedule: V columns in passes of 16, one launch per block of
+// 64 rows.  W is the private copy of V (row stride k); T holds n x 16 records.
+hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
+                      double sg, Coef* T, int64_t* info, int64_t* stop) {
+  return run_sysblk_t<double>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop);
+}
+
+// The same schedule with L, V and the records stored in FP32: the rows of a
+// block (Compute and the Apply inside the block) run in FP64 from the FP32
+// values, the Apply to other blocks' columns runs in FP32.
+hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, float* W, int64_t k,
+                          double sg, void* T, int64_t* info, int64_t* stop) {
+  return run_sysblk_t<float>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop);
 }
 
 }  // namespace chm

@@ -92,6 +92,56 @@ def test_bad_arguments_sync_and_async(nat):
     assert lib.cholmod_update_async(FAKE, FAKE, 8, 2, 8, -1, FAKE, 10, FAKE, None) == nat.ERR_ARG
 
 
+@pytest.mark.parametrize("kw", [
+    dict(n=-1), dict(k=-1), dict(ldl=7), dict(sigma=0), dict(L=None), dict(V=None),
+    dict(ws=None), dict(wsb=16), dict(info=None), dict(info=ctypes.c_void_p(0x100004)),
+    dict(ws=ctypes.c_void_p(0x100010)),
+])
+def test_f32s_bad_arguments_rejected_on_host(nat, kw):
+    a = dict(L=FAKE, V=FAKE, n=8, k=2, ldl=8, sigma=1, ws=FAKE, wsb=1 << 20, info=FAKE)
+    a.update(kw)
+    lib = nat.load()
+    assert lib.cholmod_update_f32s_async(a["L"], a["V"], a["n"], a["k"], a["ldl"], a["sigma"],
+                                         a["ws"], a["wsb"], a["info"], None) == nat.ERR_ARG
+    assert lib.cholmod_update_f32s(FAKE, FAKE, 8, 2, 4, 1, None) == nat.ERR_ARG
+    assert lib.cholmod_update_f32s(FAKE, None, 8, 2, 8, -1, None) == nat.ERR_ARG
+
+
+def _desc(nat, n=8, k=2, ldl=None, sigma=1, dtype=0, L=0x100000, V=0x200000):
+    return nat.Desc(L, V, n, k, n if ldl is None else ldl, sigma, dtype)
+
+
+def test_batched_workspace_and_validation(nat):
+    lib = nat.load()
+    arr = (nat.Desc * 3)(_desc(nat), _desc(nat, n=100, k=33), _desc(nat, n=70, k=5, dtype=1))
+    need = lib.cholmod_workspace_bytes_batched(arr, 3)
+    single = sum(nat.workspace_bytes(n, k, t) for n, k, t in [(8, 2, 0), (100, 33, 0), (70, 5, 1)])
+    assert need >= single and need % 256 == 0
+    for bad in [dict(n=-1), dict(ldl=3), dict(sigma=0), dict(dtype=5), dict(L=None)]:
+        b = (nat.Desc * 2)(_desc(nat), _desc(nat, **bad))
+        assert lib.cholmod_workspace_bytes_batched(b, 2) == 0
+        assert lib.cholmod_update_batched(b, 2, FAKE, 1 << 30, FAKE, None) == nat.ERR_ARG
+    assert lib.cholmod_update_batched(arr, -1, FAKE, 1 << 30, FAKE, None) == nat.ERR_ARG
+    assert lib.cholmod_update_batched(arr, 3, FAKE, need - 1, FAKE, None) == nat.ERR_ARG
+    assert lib.cholmod_update_batched(arr, 3, FAKE, need, None, None) == nat.ERR_ARG
+    assert lib.cholmod_update_batched(arr, 3, ctypes.c_void_p(0x100010), need, FAKE,
+                                      None) == nat.ERR_ARG
+    assert lib.cholmod_update_batched(arr, 0, None, 0, None, None) == nat.OK
+
+
+def test_server_bad_config_rejected_on_host(nat):
+    lib = nat.load()
+    out = ctypes.c_void_p()
+    for cfg in [nat.ServerCfg(16, 0, 0), nat.ServerCfg(1 << 20, -1, 0),
+                nat.ServerCfg(1 << 20, 70000, 0)]:
+        assert lib.cholmod_server_create(ctypes.byref(cfg), ctypes.byref(out)) == nat.ERR_ARG
+    assert lib.cholmod_server_create(None, ctypes.byref(out)) == nat.ERR_ARG
+    assert lib.cholmod_server_add_factor(None, FAKE, 4, 4, 0, None) == nat.ERR_ARG
+    assert lib.cholmod_server_poll(None, 1, None, None) == nat.ERR_ARG
+    assert lib.cholmod_server_drain(None) == nat.ERR_ARG
+    assert lib.cholmod_server_destroy(None) == nat.ERR_ARG
+
+
 def test_python_binding_rejects_bad_tensors():
     import torch
     import paper_1011_1173_amd as chm

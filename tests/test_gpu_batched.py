@@ -1,0 +1,103 @@
+"""Batched modification (cholmod_update_batched) of uneven factors.
+
+Each factor of a batch runs the same blocking and the same per-element
+operations as the single-factor entry point of its storage type, so its
+result must equal the single-factor result bit for bit; the single-factor
+path itself is checked against the oracle elsewhere, and here again within
+the FP64 (1e-12) or FP32-storage (1e-5) bound.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import RESID_TOL, print_case, problem, rel_diff
+
+pytestmark = pytest.mark.gpu
+F32_TOL = 1e-5
+
+
+def make_case(orc, n, k, sigma, f32, seed):
+    L, V = problem(n, k, seed)
+    if f32:
+        V = V.astype(np.float32).astype(np.float64)
+    if sigma < 0:
+        L, st, _ = orc.modify(L, V, +1)
+        assert st == 0
+    if f32:
+        L = L.astype(np.float32).astype(np.float64)
+    return L, V
+
+
+def to_dev(a, f32):
+    return torch.from_numpy(np.ascontiguousarray(a.astype(np.float32 if f32 else np.float64))).cuda()
+
+
+def run_both(cases):
+    """cases: [(L, V, sigma, f32)] -> (single results, batched results, batched statuses)."""
+    import paper_1011_1173_amd as chm
+    single, stat1 = [], []
+    for L, V, sg, f32 in cases:
+        Ld, Vd = to_dev(L, f32), to_dev(V, f32)
+        stat1.append(chm.update_async(Ld, Vd, sg).status())
+        single.append(Ld.cpu().numpy().astype(np.float64))
+    Ls = [to_dev(L, f32) for L, _, _, f32 in cases]
+    Vs = [to_dev(V, f32) for _, V, _, f32 in cases]
+    stats = chm.update_batched(Ls, Vs, [c[2] for c in cases])
+    batched = [L.cpu().numpy().astype(np.float64) for L in Ls]
+    return single, stat1, batched, stats
+
+
+MIXED = [(1, 1, 1, False), (5, 3, -1, False), (63, 16, 1, True), (64, 16, -1, False),
+         (65, 1, 1, False), (200, 17, -1, True), (130, 33, 1, False), (700, 16, 1, False),
+         (333, 8, -1, True), (97, 2, 1, True)]
+
+
+def test_batched_equals_single_bitwise(orc):
+    print_case("batched-mixed", count=len(MIXED))
+    cases = [make_case(orc, n, k, sg, f32, 5000 + i) + (sg, f32)
+             for i, (n, k, sg, f32) in enumerate(MIXED)]
+    single, stat1, batched, stats = run_both(cases)
+    for i, ((L, V, sg, f32), a, b) in enumerate(zip(cases, single, batched)):
+        assert stat1[i][0] == 0 and stats[i][0] == 0, (i, stat1[i], stats[i])
+        assert np.array_equal(a, b), "factor %d: max |diff| %g" % (i, np.abs(a - b).max())
+        ref, ost, _ = orc.modify(L, V, sg)
+        assert ost == 0
+        assert rel_diff(b, ref) <= (F32_TOL if f32 else RESID_TOL), i
+
+
+def test_batched_failure_stays_in_its_factor(orc):
+    print_case("batched-failure")
+    n, k, r = 120, 3, 70
+    Lf, _ = problem(n, 1, seed=41)
+    Vf = np.zeros((n, k))
+    Vf[:, 0] = 2.0 * Lf[r, :n]
+    _, ost, oinfo = orc.modify(Lf, Vf, -1)
+    assert ost == orc.NOT_PD
+    cases = [make_case(orc, 150, 16, 1, False, 61) + (1, False),
+             (Lf, Vf, -1, False),
+             make_case(orc, 90, 5, -1, True, 62) + (-1, True)]
+    single, stat1, batched, stats = run_both(cases)
+    assert stats[0][0] == 0 and stats[2][0] == 0
+    st, row, col = stats[1]
+    assert st == orc.NOT_PD and row * k + col == oinfo
+    assert np.array_equal(single[0], batched[0]) and np.array_equal(single[2], batched[2])
+    assert np.array_equal(single[1][:r], batched[1][:r])
+
+
+def test_batched_uneven_pool(orc):
+    """A smaller pool in the shape of the batched workload: n ~ U{64..1024},
+    k ~ U{1..32}, half updates and half downdates, FP64 and FP32 storage."""
+    rng = np.random.default_rng(7)
+    count = 24
+    print_case("batched-pool", count=count)
+    cases = []
+    for i in range(count):
+        n = int(rng.integers(64, 1025))
+        k = int(rng.integers(1, 33))
+        sg = 1 if i % 2 == 0 else -1
+        f32 = i % 3 == 0
+        cases.append(make_case(orc, n, k, sg, f32, 7000 + i) + (sg, f32))
+    single, stat1, batched, stats = run_both(cases)
+    for i in range(count):
+        assert stat1[i][0] == 0 and stats[i][0] == 0, i
+        assert np.array_equal(single[i], batched[i]), i
