@@ -1,0 +1,77 @@
+"""Served mode (cholmod_server_*): results equal the same requests applied
+one at a time through the single-factor entry points, bit for bit; failures
+and oversized requests are reported per request."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import print_case, problem
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a, f32):
+    return torch.from_numpy(np.ascontiguousarray(a.astype(np.float32 if f32 else np.float64))).cuda()
+
+
+def test_server_equals_sequential():
+    import paper_1011_1173_amd as chm
+    rng = np.random.default_rng(11)
+    shapes = [(300, False), (129, True), (64, False), (1000, False), (77, True)]
+    print_case("server", factors=len(shapes))
+    base = [problem(n, 1, 900 + i)[0] for i, (n, _) in enumerate(shapes)]
+    # a request sequence: each factor gets updates, then downdates of some of them
+    reqs = []
+    for it in range(4):
+        for f, (n, f32) in enumerate(shapes):
+            k = int(rng.integers(1, 33))
+            V = rng.standard_normal((n, k)) / np.sqrt(n)
+            reqs.append((f, V, +1))
+    for f, (n, f32) in enumerate(shapes):
+        ups = [r for r in reqs if r[0] == f and r[2] > 0]
+        reqs.append((f, ups[0][1], -1))
+        reqs.append((f, ups[2][1], -1))
+    # sequential reference through the single-factor path
+    ref = [dev(b, f32) for b, (_, f32) in zip(base, shapes)]
+    for f, V, sg in reqs:
+        st, _, _ = chm.update_async(ref[f], dev(V, shapes[f][1]), sg).status()
+        assert st == 0
+    # served
+    Ls = [dev(b, f32) for b, (_, f32) in zip(base, shapes)]
+    with chm.Server(ws_bytes=64 << 20, max_batch=8) as srv:
+        ids = [srv.add_factor(L) for L in Ls]
+        tickets = [srv.submit(ids[f], dev(V, shapes[f][1]), sg) for f, V, sg in reqs]
+        srv.drain()
+        res = [srv.poll(t) for t in tickets]
+    for (st, lat) in res:
+        assert st == 0 and lat > 0.0
+    for f in range(len(shapes)):
+        a = ref[f].cpu().numpy()
+        b = Ls[f].cpu().numpy()
+        assert np.array_equal(a, b), "factor %d" % f
+
+
+def test_server_reports_failures_per_request(orc):
+    import paper_1011_1173_amd as chm
+    print_case("server-fail")
+    n, r = 100, 40
+    L, _ = problem(n, 1, seed=71)
+    Vbad = np.zeros((n, 2))
+    Vbad[:, 0] = 2.0 * L[r, :n]
+    _, ost, oinfo = orc.modify(L, Vbad, -1)
+    assert ost == orc.NOT_PD
+    L2, V2 = problem(200, 16, seed=72)
+    big = torch.zeros(5000, 5000, dtype=torch.float64, device="cuda")
+    big.diagonal().fill_(1.0)
+    with chm.Server(ws_bytes=4 << 20, max_batch=4) as srv:
+        a = srv.add_factor(dev(L, False))
+        b = srv.add_factor(dev(L2, False))
+        c = srv.add_factor(big)
+        t1 = srv.submit(a, dev(Vbad, False), -1)
+        t2 = srv.submit(b, dev(V2, False), +1)
+        t3 = srv.submit(c, torch.zeros(5000, 16, dtype=torch.float64, device="cuda"), +1)
+        srv.drain()
+        s1, s2, s3 = srv.poll(t1), srv.poll(t2), srv.poll(t3)
+    assert s1[0] == chm.ERR_NOT_PD
+    assert s2[0] == 0
+    assert s3[0] == chm.ERR_ARG  # needs more workspace than one batch slot has
