@@ -24,6 +24,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+PROFILE = os.path.join(ROOT, "profiles", "k_sb_block_n5000_k16.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1011_1173_amd", "csrc", "sysblk.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), or None
+    if the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines()
+                if line.startswith(("traffic_bytes_per_launch:", "kernel_sha256_prefix:")))
+    if vals.get("kernel_sha256_prefix", "").strip() != sha:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -34,6 +53,13 @@ def parse():
     ap.add_argument("--n", type=int, default=5000)
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--mode", choices=["headline", "served"], default="headline",
+                    help="headline: one factor, n=5000, k=16 (default); served: a pool of "
+                         "factors fed by Poisson arrivals through the served mode")
+    ap.add_argument("--served-seconds", type=float, default=3.0,
+                    help="served mode: arrival window per load level")
+    ap.add_argument("--served-factors", type=int, default=64)
+    ap.add_argument("--served-max-n", type=int, default=16384)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy before the timed region, as the "
                          "reference dispatch for hardware byte counters")
@@ -63,6 +89,128 @@ def cpu_baseline(L, V, budget_s=10.0):
                       "%.1f s on one host core" % (mods, V.shape[1], L.shape[0], dt)}
 
 
+def served(args):
+    """Served workload: a pool of factors with sizes cycled over {1024, 2048,
+    4096, 8192, 16384}, each with 4 prior V's already added (untimed).  A
+    request is an update of one factor by a new V (k ~ U{1..32}, N(0,1)/sqrt(n))
+    followed by the downdate of that factor's oldest added V; its latency runs
+    from its arrival to the completion of both.  Saturated throughput is
+    measured with a burst; then Poisson arrivals at 25/50/75/90% of it."""
+    import random
+    import torch
+    import paper_1011_1173_amd as chm
+    from paper_1011_1173_amd import inputs
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sizes = [s for s in (1024, 2048, 4096, 8192, 16384) if s <= args.served_max_n]
+    nf = args.served_factors
+    rng = random.Random(5)
+    factors, windows = [], []
+    for f in range(nf):
+        n = sizes[f % len(sizes)]
+        factors.append(inputs.spd_factor(n, seed=5 + f, device="cuda"))
+        windows.append([])
+    torch.cuda.synchronize()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(12345)
+
+    def new_v(n):
+        k = rng.randint(1, 32)
+        return torch.randn(n, k, generator=gen, device="cuda", dtype=torch.float64) / math.sqrt(n)
+
+    for f, L in enumerate(factors):  # prior V's, untimed
+        for _ in range(4):
+            V = new_v(L.shape[0])
+            chm.update(L, V, +1)
+            windows[f].append(V)
+    torch.cuda.synchronize()
+    dense_gb = sum(8.0 * L.shape[0] * L.shape[1] for L in factors) / 1e9
+    srv = chm.Server(ws_bytes=6 << 30, max_batch=nf)
+    ids = [srv.add_factor(L) for L in factors]
+    req_bytes = []
+
+    def submit_pair(f):
+        n = factors[f].shape[0]
+        V = new_v(n)
+        old = windows[f].pop(0)
+        windows[f].append(V)
+        t1 = srv.submit(ids[f], V, +1)
+        t2 = srv.submit(ids[f], old, -1)
+        req_bytes.append(2 * 8.0 * n * (n + 1))
+        return t1, t2
+
+    def wait_all(pairs):
+        lat = []
+        pend = list(pairs)
+        while pend:
+            nxt = []
+            for lag, t1, t2 in pend:
+                r1 = srv.poll(t1)
+                if r1 is None:
+                    nxt.append((lag, t1, t2))
+                    continue
+                r2 = srv.poll(t2)
+                while r2 is None:
+                    time.sleep(2e-5)
+                    r2 = srv.poll(t2)
+                assert r1[0] == 0 and r2[0] == 0, (r1, r2)
+                lat.append(r2[1] + lag)  # lag: arrival to submission
+            pend = nxt
+            if pend:
+                time.sleep(5e-5)
+        return lat
+
+    # saturated throughput: a burst of 2 requests per factor
+    burst = 2 * nf
+    t0 = time.perf_counter()
+    pairs = []
+    for i in range(burst):
+        t1, t2 = submit_pair(i % nf)
+        pairs.append((0.0, t1, t2))
+    srv.drain()
+    sat_s = time.perf_counter() - t0
+    wait_all(pairs)
+    sat_rate = burst / sat_s  # request pairs per second
+    levels = []
+    for frac in (0.25, 0.50, 0.75, 0.90):
+        rate = frac * sat_rate
+        pairs, arrivals = [], []
+        t_start = time.perf_counter()
+        t_next = t_start
+        req_bytes.clear()
+        while True:
+            t_next += rng.expovariate(rate)
+            if t_next - t_start > args.served_seconds:
+                break
+            while time.perf_counter() < t_next:
+                pass
+            f = rng.randrange(nf)
+            t_sub = time.perf_counter()
+            t1, t2 = submit_pair(f)
+            # latency counts from the arrival time; add the submission lag
+            pairs.append((t_sub - t_next, t1, t2))
+        srv.drain()
+        span = time.perf_counter() - t_start
+        lat = sorted(wait_all(pairs))
+        cnt = len(lat)
+        levels.append({"load": frac, "offered_pairs_per_s": rate, "pairs": cnt,
+                       "updates_per_s": 2.0 * cnt / span,
+                       "p50_ms": 1e3 * lat[cnt // 2] if cnt else None,
+                       "p99_ms": 1e3 * lat[min(cnt - 1, int(0.99 * cnt))] if cnt else None,
+                       "effective_GBps": sum(req_bytes) / span / 1e9})
+    srv.close()
+    out = {"metric": "served p50/p99 latency (update + downdate of the oldest V per request)",
+           "value": levels[-1]["p99_ms"], "unit": "ms (p99 at 90% load)", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "served pool: %d factors, n cycled over %s, 4 prior V's each, "
+                                  "k ~ U{1..32}, Poisson arrivals" % (nf, sizes),
+                      "dense_GB": dense_gb},
+           "saturated_pairs_per_s": sat_rate, "levels": levels}
+    print(json.dumps(out))
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -70,6 +218,8 @@ def main():
               "nothing here uses more than one device (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
         return 2
+    if args.mode == "served":
+        return served(args)
     import torch
     import paper_1011_1173_amd as chm
     from paper_1011_1173_amd import inputs
@@ -89,9 +239,10 @@ def main():
         chm.update_async(L, V, -1, stream=stream, workspace=ws, info=info[1:2])
 
     if args.calibrate_copy:
+        # one elementwise kernel that reads 256 MiB and writes 256 MiB
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
@@ -150,7 +301,8 @@ def main():
                           "max": per_sorted[-1]},
         "rank1_equivalent_per_s": 2.0 * K * k / (total_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if (n, k) == (5000, 16) else None,
                      "kernel": "k_sb_block (one launch per 64-row block)",
                      "launches_per_modification": launches + 1,
                      "avg_launch_us": avg_launch_us,

@@ -82,6 +82,12 @@ struct Band {
   double lo, hi, d, pad;
 };
 
+// Lane 0's other inputs at step t: the originals L(t-1, t+1) and L(t, t+1)
+// for the rows wave 0 applies to column t+1.
+struct Fill {
+  double lo, hi;
+};
+
 struct SbLds {
   double Lb[kBR][kBR + 1];  // the block's original upper triangle
   union {
@@ -92,8 +98,10 @@ struct SbLds {
   double Hb[kKP][2][kBR];   // V_j[m] after each helper rotation, by step parity
   double X[2][2][kBR];      // helper h -> h+1, by step parity
   Band Lc[kRRows];          // wave 0 results by row + 16
-  DiagPre dg[kBR];
+  DiagPre dg[kRRows];       // by row; rows >= bbc unused
+  Fill fl[kRRows];           // by step; steps with t + 1 >= bbc unused
   int64_t lim;              // first failing row known at launch
+  int fail;                 // first failing (row * 16 + column) of the block
 };
 
 __device__ __forceinline__ double sb_shr1(double x, double fill) {
@@ -122,57 +130,116 @@ __device__ __forceinline__ RotRec identity_rec() {
   return r;
 }
 
-// sh.R <- identity records, except the records of rows [p, p + rows)
-// (columns m < kc) at row offset kPad.
+// Global inputs of a workgroup are loaded in two phases: every load is
+// issued into registers first, then everything is stored to LDS, so that
+// the loads cost one memory round trip instead of one per loop iteration.
+constexpr int kRecPerThread = kRRows * kKP / kThreads;  // 6
+constexpr int kTilePerThread = kBR * kBR / kThreads;    // 16
+
+// Records of rows [p, p + rows) (columns m < kc) at row offset kPad, identity
+// records everywhere else.
 template <typename ST>
-__device__ __forceinline__ void load_records(SbLds& sh, const GRec<ST>* __restrict__ T, int64_t p,
-                                             int rows, int kc) {
-  for (int idx = threadIdx.x; idx < kRRows * kKP; idx += kThreads) {
-    const int rr = idx >> 4, m = idx & 15, r = rr - kPad;
-    RotRec rec = identity_rec();
-    if (r >= 0 && r < rows && m < kc) {
-      const GRec<ST> g = T[(p + r) * kKP + m];
-      rec.c = g.c; rec.s = g.s; rec.ic = g.ic; rec.ss = g.ss;
-    }
-    sh.R[rr][m] = rec;
+struct RecRegs {
+  GRec<ST> g[kRecPerThread];
+};
+
+template <typename ST>
+__device__ __forceinline__ void records_issue(RecRegs<ST>& rg, const GRec<ST>* __restrict__ T,
+                                              int64_t p, int rows, int kc) {
+#pragma unroll
+  for (int q = 0; q < kRecPerThread; ++q) {
+    const int idx = threadIdx.x + q * kThreads, rr = idx >> 4, m = idx & 15, r = rr - kPad;
+    GRec<ST> g;
+    g.c = (ST)1; g.s = (ST)0; g.ic = (ST)1; g.ss = (ST)0;
+    if (r >= 0 && r < rows && m < kc) g = T[(p + r) * kKP + m];
+    rg.g[q] = g;
   }
 }
 
-// Apply the records in sh.R (rows [pa, pa + 64)) to columns [j0, j0 + ncols).
-// HEAD: V of those columns goes to sh.Hb parity 1 (the chain's initial
-// values); otherwise back to W.  The caller has filled sh.R.  The arithmetic
-// runs in the storage type ST (the records hold ST values).
-template <bool HEAD, int SG, typename ST>
-__device__ __forceinline__ void apply_tile(SbLds& sh, ST* __restrict__ L, int64_t ldl,
-                                           ST* __restrict__ W, int64_t ldw, int kc,
+template <typename ST>
+__device__ __forceinline__ void records_stage(SbLds& sh, const RecRegs<ST>& rg) {
+#pragma unroll
+  for (int q = 0; q < kRecPerThread; ++q) {
+    const int idx = threadIdx.x + q * kThreads;
+    RotRec rec;
+    rec.c = rg.g[q].c; rec.s = rg.g[q].s; rec.ic = rg.g[q].ic; rec.ss = rg.g[q].ss;
+    sh.R[idx >> 4][idx & 15] = rec;
+  }
+}
+
+// An apply tile: rows [pa, pa + 64) x columns [j0, j0 + ncols) of L, and the
+// V values of this thread's four columns (lane g of group grp: columns
+// grp + 16 q, column g of V).
+template <typename ST>
+struct TileRegs {
+  ST a[kTilePerThread];
+  ST w[4];
+};
+
+template <typename ST>
+__device__ __forceinline__ void tile_issue(TileRegs<ST>& tr, const ST* __restrict__ L, int64_t ldl,
+                                           const ST* __restrict__ W, int64_t ldw, int kc,
                                            int64_t pa, int64_t j0, int ncols) {
   const int tid = threadIdx.x;
-  const int g = tid & 15, grp = tid >> 4;  // lane g of group grp: columns grp + 16 q
-  for (int idx = tid; idx < kBR * kBR; idx += kThreads) {
-    const int r = idx >> 6, c = idx & 63;
-    sh.A[r][c] = c < ncols ? (double)L[(pa + r) * ldl + j0 + c] : 0.0;
+#pragma unroll
+  for (int q = 0; q < kTilePerThread; ++q) {
+    const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
+    tr.a[q] = c < ncols ? L[(pa + r) * ldl + j0 + c] : (ST)0;
   }
-  ST w[4];
+  const int g = tid & 15, grp = tid >> 4;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int c = grp + 16 * q;
-    w[q] = (c < ncols && g < kc) ? W[(j0 + c) * ldw + g] : (ST)0;
+    tr.w[q] = (c < ncols && g < kc) ? W[(j0 + c) * ldw + g] : (ST)0;
   }
-  __syncthreads();
-  ST xs[4] = {0, 0, 0, 0};
+}
+
+template <typename ST>
+__device__ __forceinline__ void tile_stage(SbLds& sh, const TileRegs<ST>& tr) {
+#pragma unroll
+  for (int q = 0; q < kTilePerThread; ++q) {
+    const int idx = threadIdx.x + q * kThreads;
+    sh.A[idx >> 6][idx & 63] = (double)tr.a[q];
+  }
+}
+
+// Apply the records in sh.R (rows [pa, pa + 64)) to columns [j0, j0 + ncols)
+// of the tile staged in sh.A, with this thread's V values w.  HEAD: V of
+// those columns goes to sh.Hb parity 1 (the chain's initial values);
+// otherwise back to W.  The caller has staged sh.R and sh.A and
+// synchronised.  The arithmetic runs in the storage type ST (the records
+// hold ST values).
+template <bool HEAD, int SG, typename ST, int KCF>
+__device__ __forceinline__ void apply_tile(SbLds& sh, ST* __restrict__ L, int64_t ldl,
+                                           ST* __restrict__ W, int64_t ldw, int kc_,
+                                           int64_t pa, int64_t j0, int ncols, const ST (&w0)[4]) {
+  const int kc = KCF ? KCF : kc_;
+  const int tid = threadIdx.x;
+  const int g = tid & 15, grp = tid >> 4;  // lane g of group grp: columns grp + 16 q
+  ST w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) w[q] = w0[q];
+  // xin: lane 0 of a group takes row s of the tile, lane g > 0 the value
+  // lane g-1 produced at sub-step s-1 (the DPP shift's fill is the next row).
+  // The record and the tile row of sub-step s+1 are read during sub-step s
+  // (a tile row is read before lane kc-1 overwrites it with its final value:
+  // row s+2 is read at sub-step s, final at sub-step s+1+kc).
+  ST xin[4], nxt[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    xin[q] = (ST)sh.A[0][grp + 16 * q];
+    nxt[q] = (ST)sh.A[1][grp + 16 * q];
+  }
+  const RotRec* rp = &sh.R[kPad - g][g];  // record of row s - g at rp[s * kKP]
+  RotRec cf = rp[0];
   const int S = kBR + kc - 1;
   for (int s = 0; s < S; ++s) {
     const int r = s - g;
-    ST xin[4];
-    if (g == 0) {
-      const int rs = imin(s, kBR - 1);
+    const RotRec cfn = rp[imin(s + 1, kBR + kKP - 1 + g) * kKP];  // row <= 79
+    const int rn2 = imin(s + 2, kBR - 1);
+    ST nxt2[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) xin[q] = (ST)sh.A[rs][grp + 16 * q];
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) xin[q] = xs[q];
-    }
-    const RotRec& cf = sh.R[imin(r, kBR + kKP - 1) + kPad][g];  // r >= -15
+    for (int q = 0; q < 4; ++q) nxt2[q] = (ST)sh.A[rn2][grp + 16 * q];
     const ST c = (ST)cf.c, sn = (ST)cf.s, ic = (ST)cf.ic;
     ST x[4];
 #pragma unroll
@@ -185,11 +252,16 @@ __device__ __forceinline__ void apply_tile(SbLds& sh, ST* __restrict__ L, int64_
       for (int q = 0; q < 4; ++q) sh.A[r][grp + 16 * q] = x[q];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) xs[q] = sb_shr1(x[q], (ST)0);
+    for (int q = 0; q < 4; ++q) {
+      xin[q] = sb_shr1(x[q], nxt[q]);
+      nxt[q] = nxt2[q];
+    }
+    cf = cfn;
   }
   __syncthreads();
-  for (int idx = tid; idx < kBR * kBR; idx += kThreads) {
-    const int r = idx >> 6, c = idx & 63;
+#pragma unroll
+  for (int q = 0; q < kTilePerThread; ++q) {
+    const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
     if (c < ncols) L[(pa + r) * ldl + j0 + c] = (ST)sh.A[r][c];
   }
 #pragma unroll
@@ -208,8 +280,8 @@ __device__ __forceinline__ void apply_tile(SbLds& sh, ST* __restrict__ L, int64_
 // that the four roles share registers.
 constexpr int kSt = 13;
 
-// Wave 0 layout: st[0] radicand and st[1] 1/L_ii from lane m-1, st[2] L_ii
-// of the next row (used by lane 0), st[3] V_i[m] for this step's Compute,
+// Wave 0 layout: st[0] radicand, st[1] 1/L_ii and st[2] L_ii from lane m-1
+// (lane 0: the row's original diagonal), st[3] V_i[m] for this step's Compute,
 // st[4], st[5] L(i-1, i+1) and L(i, i+1) rotated through columns < m,
 // st[6..8] this lane's record {c, s, 1/c} of row i-1.
 __device__ __forceinline__ void chain_init(SbLds& sh, double (&st)[kSt], int lane, int bbc) {
@@ -218,8 +290,8 @@ __device__ __forceinline__ void chain_init(SbLds& sh, double (&st)[kSt], int lan
   st[1] = d0.il;
   st[2] = d0.l;
   st[3] = sh.Hb[lane & 15][1][0];
-  st[4] = 0.0;
-  st[5] = (lane == 0 && bbc > 1) ? sh.Lb[0][1] : 0.0;
+  st[4] = sh.fl[0].lo;
+  st[5] = sh.fl[0].hi;
   st[6] = 1.0;
   st[7] = 0.0;
   st[8] = 1.0;
@@ -227,21 +299,21 @@ __device__ __forceinline__ void chain_init(SbLds& sh, double (&st)[kSt], int lan
   for (int u = 9; u < kSt; ++u) st[u] = 0.0;
 }
 
-// One step of wave 0, lanes m < kc.  CHECK: the pipeline is filling or
-// draining (some lane has i < 0, or i + 1 >= bbc).
+// One step of wave 0.  All 64 lanes compute; lanes m >= kc carry garbage
+// and send their LDS writes to rows nobody reads (record row kRRows - 1,
+// band row 0).  CHECK: the pipeline is filling or draining (some lane has
+// i < 0, or i + 1 >= bbc).
 template <bool CHECK, int SG>
-__device__ __forceinline__ void chain_step(SbLds& sh, double (&st)[kSt], int& fkey, int t, int m,
+__device__ __forceinline__ void chain_step(SbLds& sh, double (&st)[kSt], int t, int m, int kc,
                                            int bbc) {
   const int i = t - m;
   const int jj = i + 1;
-  double Wc = sh.Hb[m][(t - 1) & 1][jj & 63];
-  const DiagPre dn = sh.dg[imin(t + 1, kBR - 1)];
-  const int cn = imin(t + 2, kBR - 1);
-  const double f0 = sh.Lb[imin(t, kBR - 1)][cn];
-  const double f1 = sh.Lb[imin(t + 1, kBR - 1)][cn];
+  const bool act = m < kc;
+  double Wc = sh.Hb[m & 15][(t - 1) & 1][jj & 63];
+  const DiagPre dn = sh.dg[t + 1];  // t + 1 < 80
+  const Fill fn = sh.fl[t + 1];
   // Compute(i, m)
-  const double tpi = st[0], ili = st[1];
-  const double lin = (m == 0) ? st[2] : tpi * ili;
+  const double tpi = st[0], ili = st[1], lin = st[2];
   const double v = st[3];
   const double tt = __builtin_fma(SG * v, v, tpi);
   const double y = rsqrt_refined(tt);
@@ -249,13 +321,10 @@ __device__ __forceinline__ void chain_step(SbLds& sh, double (&st)[kSt], int& fk
   const double s = v * ili;
   const double c = ww * ili;
   const double ic = lin * y;
-  const bool valid = !CHECK || (i >= 0 && i < bbc);
-  const int code =
-      (m == 0 && !(lin > 0.0)) ? (int)kCodeBadDiag : (!(tt > 0.0) ? (int)kCodeNotPD : 0);
-  if (valid && code != 0) fkey = imin(fkey, (i << 2) | code);
   RotRec cur;
   cur.c = c; cur.s = s; cur.ic = ic; cur.ss = SG * s;
-  sh.R[CHECK ? (valid ? i + kPad : kRRows - 1) : i + kPad][m] = cur;
+  const bool rec_ok = act && (!CHECK || (i >= 0 && i < bbc));
+  sh.R[rec_ok ? i + kPad : kRRows - 1][m & 15] = cur;
   // rows i-1 (record of the previous step) and i applied to column jj
   const double pc = st[6], ps = st[7], pic = st[8];
   const double x0 = __builtin_fma(SG * ps, Wc, st[4]) * pic;
@@ -264,7 +333,7 @@ __device__ __forceinline__ void chain_step(SbLds& sh, double (&st)[kSt], int& fk
   Wc = __builtin_fma(-s, x1, c * Wc);
   Band b;
   b.lo = x0; b.hi = x1; b.d = ww; b.pad = 0.0;
-  sh.Lc[CHECK ? imax(imin(i + kPad, kRRows - 1), 0) : i + kPad] = b;
+  sh.Lc[act ? (CHECK ? imax(imin(i + kPad, kRRows - 1), 0) : i + kPad) : 0] = b;
   if (CHECK) {
     const bool started = i >= 0;
     st[3] = started ? Wc : st[3];
@@ -278,11 +347,11 @@ __device__ __forceinline__ void chain_step(SbLds& sh, double (&st)[kSt], int& fk
     st[8] = ic;
   }
   // to lane m+1 (lane 0 takes row t+1's originals)
-  st[4] = sb_shr1(x0, f0);
-  st[5] = sb_shr1(x1, f1);
+  st[4] = sb_shr1(x0, fn.lo);
+  st[5] = sb_shr1(x1, fn.hi);
   st[0] = sb_shr1(tt, dn.t);
   st[1] = sb_shr1(y, dn.il);
-  st[2] = dn.l;
+  st[2] = sb_shr1(ww, dn.l);  // L_ii after column m = t * y: what tp * il gives lane m+1
 }
 
 // Helper wave layout (columns [MLO, MLO + CNT) of V, lane jj = block column):
@@ -299,13 +368,15 @@ __device__ __forceinline__ void helper_init(SbLds& sh, double (&st)[kSt], int jj
   st[2 * CNT] = sh.Lb[0][jj];
 }
 
-template <int H, int MLO, int CNT, int SG>
-__device__ __forceinline__ void helper_step(SbLds& sh, double (&st)[kSt], int t, int jj, int kc) {
+template <int H, int MLO, int CNT, int SG, int KCF>
+__device__ __forceinline__ void helper_step(SbLds& sh, double (&st)[kSt], int t, int jj,
+                                            int kc_) {
+  const int kc = KCF ? KCF : kc_;
   double c[CNT], sn[CNT], ic[CNT];
 #pragma unroll
   for (int u = 0; u < CNT; ++u) {
-    const int rr = imin(t - 1 - MLO - u + kPad, kRRows - 1);  // >= 0: t >= 0, MLO + u < 16
-    const RotRec& cf = sh.R[rr][MLO + u];
+    // record row t - 1 - m + 16 lies in [0, 94): t < 80, m < 16
+    const RotRec& cf = sh.R[t - 1 - MLO - u + kPad][MLO + u];
     c[u] = cf.c;
     sn[u] = cf.s;
     ic[u] = cf.ic;
@@ -334,73 +405,99 @@ __device__ __forceinline__ void helper_step(SbLds& sh, double (&st)[kSt], int t,
 // barriers, one per step (the role is wave-uniform, so no wave enters
 // another role's loop).
 template <bool CHECK, int SG>
-__device__ __forceinline__ void chain_steps(SbLds& sh, double (&st)[kSt], int& fkey, int t0,
-                                            int t1, int lane, int kc, int bbc) {
+__device__ __forceinline__ void chain_steps(SbLds& sh, double (&st)[kSt], int t0, int t1,
+                                            int lane, int kc, int bbc) {
   for (int t = t0; t < t1; ++t) {
-    if (lane < kc) chain_step<CHECK, SG>(sh, st, fkey, t, lane, bbc);
+    chain_step<CHECK, SG>(sh, st, t, lane, kc, bbc);
     __syncthreads();
   }
 }
 
-template <int H, int MLO, int CNT, int SG>
+template <int H, int MLO, int CNT, int SG, int KCF>
 __device__ __forceinline__ void helper_steps(SbLds& sh, int nsteps, int lane, int kc) {
   double st[kSt];
   helper_init<MLO, CNT>(sh, st, lane);
   __syncthreads();
   for (int t = 0; t < nsteps; ++t) {
-    helper_step<H, MLO, CNT, SG>(sh, st, t, lane, kc);
+    helper_step<H, MLO, CNT, SG, KCF>(sh, st, t, lane, kc);
     __syncthreads();
   }
 }
 
 // Workgroup 0: head tile, then the chain of block [pc, pc + bbc).
-template <int SG, typename ST>
+template <int SG, typename ST, int KCF>
 __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t ldl,
-                                         ST* __restrict__ W, int64_t ldw, int kc,
+                                         ST* __restrict__ W, int64_t ldw, int kc_,
                                          int64_t kfull, int64_t m0, int64_t pc, int bbc,
                                          int64_t pa, GRec<ST>* __restrict__ T,
                                          int64_t* __restrict__ info,
                                          int64_t* __restrict__ stop_row, int64_t lim) {
+  const int kc = KCF ? KCF : kc_;
   const int tid = threadIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const bool head = pa >= 0 && pa < lim;
-  if (head) {
-    load_records(sh, T, pa, lim - pa < kBR ? (int)(lim - pa) : kBR, kc);
-  } else {
-    for (int idx = tid; idx < kRRows * kKP; idx += kThreads)
-      sh.R[idx >> 4][idx & 15] = identity_rec();
-  }
-  if (pc >= lim) {
-    // a failure in block b-1: finish its rows before the failure, nothing else
-    if (head) apply_tile<true, SG, ST>(sh, L, ldl, W, ldw, kc, pa, pc, bbc);
-    return;
-  }
-  for (int idx = tid; idx < kBR * kBR; idx += kThreads) {
-    const int i = idx >> 6, j = idx & 63;
-    sh.Lb[i][j] = (i < bbc && j < bbc && j >= i) ? (double)L[(pc + i) * ldl + pc + j] : 0.0;
-  }
-  if (head) {
-    apply_tile<true, SG, ST>(sh, L, ldl, W, ldw, kc, pa, pc, bbc);
-  } else {
-    for (int idx = tid; idx < kBR * kKP; idx += kThreads) {
-      const int c = idx >> 4, g = idx & 15;
-      if (g < kc) sh.Hb[g][1][c] = c < bbc ? (double)W[(pc + c) * ldw + g] : 0.0;
+  const int hrows = head ? (lim - pa < kBR ? (int)(lim - pa) : kBR) : 0;
+  const bool chain = pc < lim;  // else a failure in block b-1: finish its rows only
+  // issue every global load, then stage them in LDS
+  RecRegs<ST> rg;
+  records_issue(rg, T, pa, hrows, kc);  // all identity without a head tile
+  TileRegs<ST> tr;
+  if (head) tile_issue(tr, L, ldl, W, ldw, kc, pa, pc, bbc);
+  ST lt[kTilePerThread], wh[4];
+  if (chain) {
+#pragma unroll
+    for (int q = 0; q < kTilePerThread; ++q) {
+      const int idx = tid + q * kThreads, i = idx >> 6, j = idx & 63;
+      lt[q] = (i < bbc && j < bbc && j >= i) ? L[(pc + i) * ldl + pc + j] : (ST)0;
+    }
+    if (!head) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int idx = tid + q * kThreads, c = idx >> 4, g = idx & 15;
+        wh[q] = (g < kc && c < bbc) ? W[(pc + c) * ldw + g] : (ST)0;
+      }
     }
   }
+  records_stage(sh, rg);
+  if (head) tile_stage(sh, tr);
+  if (chain) {
+#pragma unroll
+    for (int q = 0; q < kTilePerThread; ++q) {
+      const int idx = tid + q * kThreads;
+      sh.Lb[idx >> 6][idx & 63] = (double)lt[q];
+    }
+    if (!head) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int idx = tid + q * kThreads;
+        sh.Hb[idx & 15][1][idx >> 4] = (double)wh[q];
+      }
+    }
+  }
+  __syncthreads();
+  if (head) apply_tile<true, SG, ST, KCF>(sh, L, ldl, W, ldw, kc, pa, pc, bbc, tr.w);
+  if (!chain) return;
   __syncthreads();
   // identity records for this block's rows until wave 0 writes them
   for (int idx = tid; idx < kRRows * kKP; idx += kThreads) {
     if ((idx >> 4) >= kPad) sh.R[idx >> 4][idx & 15] = identity_rec();
   }
   for (int idx = tid; idx < 2 * kBR; idx += kThreads) sh.X[idx >> 6][1][idx & 63] = 0.0;
-  if (tid < kBR) {
-    const double l = sh.Lb[tid][tid];
+  if (tid == 0) sh.fail = 0x7fffffff;
+  if (tid < kRRows) {
+    const int r = tid < kBR ? tid : kBR - 1;
+    const double l = sh.Lb[r][r];
     DiagPre d;
     d.l = l;
     d.t = l * l;
     d.il = 1.0 / l;
     d.pad = 0.0;
     sh.dg[tid] = d;
+    // lane 0 at step t applies rows t-1 and t to column t+1
+    Fill f;
+    f.lo = (tid >= 1 && tid + 1 < bbc) ? sh.Lb[tid - 1][tid + 1] : 0.0;
+    f.hi = (tid + 1 < bbc) ? sh.Lb[tid][tid + 1] : 0.0;
+    sh.fl[tid] = f;
   }
   __syncthreads();
   // steady steps [s0, s1): every lane m < kc has i >= 0 and i + 1 < bbc
@@ -408,24 +505,38 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
   const int s0 = kc - 1, s1 = imax(kc - 1, bbc - 1);
   if (wv == 0) {
     double st[kSt];
-    int fkey = 0x7fffffff;
     chain_init(sh, st, lane, bbc);
     __syncthreads();
-    chain_steps<true, SG>(sh, st, fkey, 0, s0, lane, kc, bbc);
-    chain_steps<false, SG>(sh, st, fkey, s0, s1, lane, kc, bbc);
-    chain_steps<true, SG>(sh, st, fkey, s1, nsteps, lane, kc, bbc);
-    if (lane < kc && fkey != 0x7fffffff) {
-      const int64_t i = fkey >> 2, code = fkey & 3;
-      atomicMin((unsigned long long*)info,
-                (unsigned long long)info_key((pc + i) * kfull + m0 + lane, code));
-      atomicMin((unsigned long long*)stop_row, (unsigned long long)(pc + i));
-    }
+    chain_steps<true, SG>(sh, st, 0, s0, lane, kc, bbc);
+    chain_steps<false, SG>(sh, st, s0, s1, lane, kc, bbc);
+    chain_steps<true, SG>(sh, st, s1, nsteps, lane, kc, bbc);
   } else if (wv == 1) {
-    helper_steps<0, 0, 6, SG>(sh, nsteps, lane, kc);
+    helper_steps<0, 0, 6, SG, KCF>(sh, nsteps, lane, kc);
   } else if (wv == 2) {
-    helper_steps<1, 6, 5, SG>(sh, nsteps, lane, kc);
+    helper_steps<1, 6, 5, SG, KCF>(sh, nsteps, lane, kc);
   } else {
-    helper_steps<2, 11, 5, SG>(sh, nsteps, lane, kc);
+    helper_steps<2, 11, 5, SG, KCF>(sh, nsteps, lane, kc);
+  }
+  // The first failing Compute of the block in (row, column) order.  A
+  // Compute fails iff its radicand is not > 0 (then y, w and c are NaN) or,
+  // for column 0, the original diagonal is not > 0 (then c = w / L_ii is
+  // negative, infinite or NaN); every later Compute of the same row or of a
+  // later row may be garbage, none of an earlier row is.  So the failure is
+  // the first record whose c is not a finite positive number.
+  for (int idx = tid; idx < kBR * kKP; idx += kThreads) {
+    const int r = idx >> 4, m = idx & 15;
+    if (r < bbc && m < kc) {
+      const double c = sh.R[r + kPad][m].c;
+      if (!(c > 0.0 && c < __builtin_huge_val())) atomicMin(&sh.fail, idx);
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && sh.fail != 0x7fffffff) {
+    const int r = sh.fail >> 4, m = sh.fail & 15;
+    const int64_t code = (m == 0 && !(sh.dg[r].l > 0.0)) ? kCodeBadDiag : kCodeNotPD;
+    atomicMin((unsigned long long*)info,
+              (unsigned long long)info_key((pc + r) * kfull + m0 + m, code));
+    atomicMin((unsigned long long*)stop_row, (unsigned long long)(pc + r));
   }
   // the block's triangle (diagonal and two superdiagonals from wave 0, the
   // rest from the helper holding column kc - 1 of V) and its records
@@ -454,7 +565,7 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
 // One workgroup's share of the launch for block [pc, pc + bbc) of one factor:
 // wg == 0 runs the chain, wg >= 1 applies block [pa, pa + 64) to the
 // 64-column tile wg - 1 right of the block.
-template <int SG, typename ST>
+template <int SG, typename ST, int KCF>
 __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_t ldl,
                                            ST* __restrict__ W, int64_t ldw, int kc,
                                            int64_t kfull, int64_t m0, int64_t n, int64_t pc,
@@ -467,24 +578,31 @@ __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_
   __syncthreads();
   const int64_t lim = sh.lim;
   if (wg == 0) {
-    chain_wg<SG, ST>(sh, L, ldl, W, ldw, kc, kfull, m0, pc, bbc, pa, T, info, stop_row, lim);
+    chain_wg<SG, ST, KCF>(sh, L, ldl, W, ldw, kc, kfull, m0, pc, bbc, pa, T, info, stop_row,
+                          lim);
   } else {
     if (pa < 0 || pa >= lim) return;
     const int64_t j0 = pc + bbc + (int64_t)(wg - 1) * kBR;
     const int ncols = n - j0 < kBR ? (int)(n - j0) : kBR;
-    load_records(sh, T, pa, lim - pa < kBR ? (int)(lim - pa) : kBR, kc);
-    apply_tile<false, SG, ST>(sh, L, ldl, W, ldw, kc, pa, j0, ncols);
+    RecRegs<ST> rg;
+    records_issue(rg, T, pa, lim - pa < kBR ? (int)(lim - pa) : kBR, kc);
+    TileRegs<ST> tr;
+    tile_issue(tr, L, ldl, W, ldw, kc, pa, j0, ncols);
+    records_stage(sh, rg);
+    tile_stage(sh, tr);
+    __syncthreads();
+    apply_tile<false, SG, ST, KCF>(sh, L, ldl, W, ldw, kc, pa, j0, ncols, tr.w);
   }
 }
 
-template <int SG, typename ST>
+template <int SG, typename ST, int KCF>
 __global__ __launch_bounds__(kThreads) void k_sb_block(
     ST* __restrict__ L, int64_t ldl, ST* __restrict__ W, int64_t ldw, int kc, int64_t kfull,
     int64_t m0, int64_t n, int64_t pc, int bbc, int64_t pa, GRec<ST>* __restrict__ T,
     int64_t* __restrict__ info, int64_t* __restrict__ stop_row) {
   __shared__ SbLds sh;
-  block_work<SG, ST>(sh, L, ldl, W, ldw, kc, kfull, m0, n, pc, bbc, pa, T, info, stop_row,
-                     (int)blockIdx.x);
+  block_work<SG, ST, KCF>(sh, L, ldl, W, ldw, kc, kfull, m0, n, pc, bbc, pa, T, info,
+                          stop_row, (int)blockIdx.x);
 }
 
 // Batched form: the launch of step s holds, for every factor with more than
@@ -514,20 +632,20 @@ __global__ __launch_bounds__(kThreads) void k_sb_batch(const BatchFactor* __rest
     double* W = (double*)F.W + E.m0;
     GRec<double>* T = (GRec<double>*)F.T;
     if (F.sigma > 0)
-      block_work<1, double>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+      block_work<1, double, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
                             F.info, F.stop, wg);
     else
-      block_work<-1, double>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+      block_work<-1, double, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
                              F.info, F.stop, wg);
   } else {
     float* L = (float*)F.L;
     float* W = (float*)F.W + E.m0;
     GRec<float>* T = (GRec<float>*)F.T;
     if (F.sigma > 0)
-      block_work<1, float>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+      block_work<1, float, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
                            F.info, F.stop, wg);
     else
-      block_work<-1, float>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+      block_work<-1, float, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
                             F.info, F.stop, wg);
   }
 }
@@ -560,12 +678,11 @@ hipError_t run_sysblk_t(hipStream_t st, ST* L, int64_t n, int64_t ldl, ST* W, in
       const int64_t pa = pc - kBR;  // previous block (always full), or < 0
       const int64_t rest = n - (pc + bbc);
       const unsigned grid = 1u + (pa >= 0 ? (unsigned)((rest + kBR - 1) / kBR) : 0u);
-      if (sg > 0)
-        hipLaunchKernelGGL((k_sb_block<1, ST>), dim3(grid), dim3(kThreads), 0, st, L, ldl, Wc, k,
-                           kc, k, m0, n, pc, bbc, pa, R, info, stop);
-      else
-        hipLaunchKernelGGL((k_sb_block<-1, ST>), dim3(grid), dim3(kThreads), 0, st, L, ldl, Wc,
-                           k, kc, k, m0, n, pc, bbc, pa, R, info, stop);
+      // full passes (16 columns of V) use a variant specialised on that width
+      auto kern = sg > 0 ? (kc == kKP ? k_sb_block<1, ST, kKP> : k_sb_block<1, ST, 0>)
+                         : (kc == kKP ? k_sb_block<-1, ST, kKP> : k_sb_block<-1, ST, 0>);
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, L, ldl, Wc, k, kc, k, m0, n, pc,
+                         bbc, pa, R, info, stop);
     }
   }
   return hipGetLastError();

@@ -63,7 +63,9 @@ def test_server_reports_failures_per_request(orc):
     L2, V2 = problem(200, 16, seed=72)
     big = torch.zeros(5000, 5000, dtype=torch.float64, device="cuda")
     big.diagonal().fill_(1.0)
-    with chm.Server(ws_bytes=4 << 20, max_batch=4) as srv:
+    # 1 MiB slots: the two small requests fit together; the n = 5000, k = 16
+    # request needs about 3.3 MB of workspace and can never run
+    with chm.Server(ws_bytes=1 << 20, max_batch=4) as srv:
         a = srv.add_factor(dev(L, False))
         b = srv.add_factor(dev(L2, False))
         c = srv.add_factor(big)
