@@ -19,9 +19,9 @@ namespace chm {
 hipError_t run_blocked(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
                        double sg, Coef* T, int64_t* info, int64_t* stop, bool exact);
 hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
-                      double sg, Coef* T, int64_t* info, int64_t* stop);
+                      double sg, Coef* T, int64_t* info, int64_t* stop, int32_t* flags);
 hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, float* W, int64_t k,
-                          double sg, void* T, int64_t* info, int64_t* stop);
+                          double sg, void* T, int64_t* info, int64_t* stop, int32_t* flags);
 hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
                             const BatchEntry* d_ent, const BatchStep* steps, int64_t nsteps);
 
@@ -36,8 +36,11 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 //   [0, 768)         control words: the first failing row (int64) at 0
 //   W                n*k private copy of V
 //   T                n*max(16, min(k, 64)) rotation records of 32 bytes
+//   F                one int32 per (16-column pass, 64-row block): "the
+//                    block's records are in T" flags of the fast schedule
 struct WsLayout {
-  size_t ctrl = 0, w = 0, t = 0, total = 0;
+  size_t ctrl = 0, w = 0, t = 0, f = 0, total = 0;
+  int64_t nflags = 0;
 };
 
 bool mul_ok(int64_t a, int64_t b, int64_t lim) { return a == 0 || b <= lim / a; }
@@ -54,14 +57,17 @@ bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out) {
   L.t = L.w + align_up((size_t)(n * k) * es);
   int64_t kp = k < kKPass ? k : kKPass;
   if (kp < 16) kp = 16;
-  L.total = L.t + align_up((size_t)(n * kp) * sizeof(Coef));
+  L.f = L.t + align_up((size_t)(n * kp) * sizeof(Coef));
+  L.nflags = ((n + 63) / 64) * ((k + 15) / 16);
+  L.total = L.f + align_up((size_t)L.nflags * sizeof(int32_t));
   *out = L;
   return true;
 }
 
 template <typename ST>
 __global__ void k_prepare(const ST* __restrict__ V, ST* __restrict__ W, int64_t count,
-                          int64_t* __restrict__ info, int64_t* __restrict__ stop_row) {
+                          int64_t* __restrict__ info, int64_t* __restrict__ stop_row,
+                          int32_t* __restrict__ flags, int64_t nflags) {
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i0 == 0) {
     *info = INT64_MAX;
@@ -69,6 +75,7 @@ __global__ void k_prepare(const ST* __restrict__ V, ST* __restrict__ W, int64_t 
   }
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = i0; i < count; i += stride) W[i] = V[i];
+  for (int64_t i = i0; i < nflags; i += stride) flags[i] = 0;
 }
 
 int validate(const void* L, const void* V, int64_t n, int64_t k, int64_t ldl, int sigma) {
@@ -97,6 +104,7 @@ int enqueue_f64(double* L, const double* V, int64_t n, int64_t k, int64_t ldl, i
   int64_t* stop_row = (int64_t*)(base + lay.ctrl);
   double* W = (double*)(base + lay.w);
   Coef* T = (Coef*)(base + lay.t);
+  int32_t* F = (int32_t*)(base + lay.f);
   const bool exact = (flags & CHOLMOD_FLAG_EXACT) != 0;
   const bool blocked = exact || (flags & CHOLMOD_FLAG_BLOCKED) != 0;
   const int64_t count = n * k;  // both schedules work on a private copy of V
@@ -104,7 +112,7 @@ int enqueue_f64(double* L, const double* V, int64_t n, int64_t k, int64_t ldl, i
   if (grid < 1) grid = 1;
   if (grid > 4096) grid = 4096;
   hipLaunchKernelGGL(k_prepare<double>, dim3(grid), dim3(256), 0, st, V, W, count, d_info,
-                     stop_row);
+                     stop_row, F, lay.nflags);
   if (hipGetLastError() != hipSuccess) return CHOLMOD_ERR_HIP;
   if (n == 0 || k == 0) return CHOLMOD_OK;
   const double sg = (double)sigma;
@@ -112,7 +120,7 @@ int enqueue_f64(double* L, const double* V, int64_t n, int64_t k, int64_t ldl, i
   if (blocked) {
     e = run_blocked(st, L, n, ldl, W, k, sg, T, d_info, stop_row, exact);
   } else {
-    e = run_sysblk(st, L, n, ldl, W, k, sg, T, d_info, stop_row);
+    e = run_sysblk(st, L, n, ldl, W, k, sg, T, d_info, stop_row, F);
   }
   return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
 }
@@ -131,15 +139,16 @@ int enqueue_f32s(float* L, const float* V, int64_t n, int64_t k, int64_t ldl, in
   int64_t* stop_row = (int64_t*)(base + lay.ctrl);
   float* W = (float*)(base + lay.w);
   void* T = (void*)(base + lay.t);
+  int32_t* F = (int32_t*)(base + lay.f);
   const int64_t count = n * k;
   unsigned grid = (unsigned)((count + 255) / 256);
   if (grid < 1) grid = 1;
   if (grid > 4096) grid = 4096;
   hipLaunchKernelGGL(k_prepare<float>, dim3(grid), dim3(256), 0, st, V, W, count, d_info,
-                     stop_row);
+                     stop_row, F, lay.nflags);
   if (hipGetLastError() != hipSuccess) return CHOLMOD_ERR_HIP;
   if (n == 0 || k == 0) return CHOLMOD_OK;
-  hipError_t e = run_sysblk_f32(st, L, n, ldl, W, k, (double)sigma, T, d_info, stop_row);
+  hipError_t e = run_sysblk_f32(st, L, n, ldl, W, k, (double)sigma, T, d_info, stop_row, F);
   return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
 }
 

@@ -19,11 +19,13 @@
 // step t = i + m and passes the running radicand and 1/L_ii to lane m+1 with
 // a DPP row shift.  Column j of the block needs the rotations of all earlier
 // rows of the block before it becomes the diagonal:
-//   * rows r < j - 2 are applied by three helper waves, one lane per column
+//   * rows r < j - 2 are applied by six helper waves, one lane per column
 //     j, in diagonal order: at step t a helper applies (r, m) with
 //     r + m = t - 1, whose record wave 0 wrote to LDS at step t - 1; the
-//     waves split the columns of V 6 + 5 + 5 and pass the partly rotated
-//     L_rj on through LDS.  After each rotation the helper publishes V_j[m]
+//     waves split the columns of V 3 + 3 + 3 + 3 + 2 + 2 and pass the partly
+//     rotated L_rj on through LDS.  The workgroup's 8 waves are spread over
+//     the 4 SIMDs round-robin, so wave 0 shares its SIMD only with wave 4,
+//     which idles, and the helpers pair up on the other three.  After each rotation the helper publishes V_j[m]
 //     (by step parity); the value after row j - 3 is the hand-off;
 //   * lane m of wave 0 takes that hand-off and applies rows j - 2 and j - 1
 //     itself at step j - 1 + m (the partly rotated L_rj moving from lane m
@@ -36,9 +38,10 @@
 //
 // The apply tiles (head and rest).  A tile is 64 rows (the block) by 64
 // columns.  Lane g of a 16-lane group applies rotation g of row s - g at
-// sub-step s to four columns, so each record read from LDS serves four
+// sub-step s to two columns, so each record read from LDS serves two
 // columns; the partly rotated L_rj moves to lane g+1 with a DPP row shift
-// and each lane keeps its four V_j[g] in registers.
+// and each lane keeps its two V_j[g] in registers.  Two waves per SIMD hide
+// each other's latencies.
 //
 // Failures.  After a failure at row r the contents of rows >= r are
 // unspecified, so nothing inside a block depends on a failure: the first
@@ -53,7 +56,7 @@ namespace {
 
 constexpr int kBR = 64;        // rows (and columns) of a block
 constexpr int kKP = 16;        // columns of V per pass
-constexpr int kThreads = 256;  // 4 waves
+constexpr int kThreads = 512;  // 8 waves, two per SIMD
 constexpr int kPad = 16;       // identity record rows before the block
 constexpr int kRRows = kPad + kBR + kKP;  // record rows -16 .. 79
 
@@ -96,7 +99,7 @@ struct SbLds {
   };
   RotRec R[kRRows][kKP];    // records by row + 16: identity / block rows / identity
   double Hb[kKP][2][kBR];   // V_j[m] after each helper rotation, by step parity
-  double X[2][2][kBR];      // helper h -> h+1, by step parity
+  double X[5][2][kBR];      // helper h -> h+1, by step parity
   Band Lc[kRRows];          // wave 0 results by row + 16
   DiagPre dg[kRRows];       // by row; rows >= bbc unused
   Fill fl[kRRows];           // by step; steps with t + 1 >= bbc unused
@@ -133,8 +136,9 @@ __device__ __forceinline__ RotRec identity_rec() {
 // Global inputs of a workgroup are loaded in two phases: every load is
 // issued into registers first, then everything is stored to LDS, so that
 // the loads cost one memory round trip instead of one per loop iteration.
-constexpr int kRecPerThread = kRRows * kKP / kThreads;  // 6
-constexpr int kTilePerThread = kBR * kBR / kThreads;    // 16
+constexpr int kRecPerThread = kRRows * kKP / kThreads;  // 3
+constexpr int kTilePerThread = kBR * kBR / kThreads;    // 8
+constexpr int kColsPerLane = kBR * kKP / kThreads;      // 2 columns per lane in an apply tile
 
 // Records of rows [p, p + rows) (columns m < kc) at row offset kPad, identity
 // records everywhere else.
@@ -168,12 +172,13 @@ __device__ __forceinline__ void records_stage(SbLds& sh, const RecRegs<ST>& rg) 
 }
 
 // An apply tile: rows [pa, pa + 64) x columns [j0, j0 + ncols) of L, and the
-// V values of this thread's four columns (lane g of group grp: columns
-// grp + 16 q, column g of V).
+// V values of this thread's columns (lane g of group grp: columns
+// grp + 32 q, column g of V).
+constexpr int kGroups = kThreads / 16;
 template <typename ST>
 struct TileRegs {
   ST a[kTilePerThread];
-  ST w[4];
+  ST w[kColsPerLane];
 };
 
 template <typename ST>
@@ -188,8 +193,8 @@ __device__ __forceinline__ void tile_issue(TileRegs<ST>& tr, const ST* __restric
   }
   const int g = tid & 15, grp = tid >> 4;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int c = grp + 16 * q;
+  for (int q = 0; q < kColsPerLane; ++q) {
+    const int c = grp + kGroups * q;
     tr.w[q] = (c < ncols && g < kc) ? W[(j0 + c) * ldw + g] : (ST)0;
   }
 }
@@ -203,6 +208,37 @@ __device__ __forceinline__ void tile_stage(SbLds& sh, const TileRegs<ST>& tr) {
   }
 }
 
+// Records published by the chain workgroup of the same launch are written
+// and read with device-coherent (agent-scope) accesses, so that they are
+// seen across the GPU's separate L2 caches.
+template <typename ST>
+__device__ __forceinline__ void records_issue_coherent(RecRegs<ST>& rg,
+                                                       const GRec<ST>* __restrict__ T, int64_t p,
+                                                       int rows, int kc) {
+#pragma unroll
+  for (int q = 0; q < kRecPerThread; ++q) {
+    const int idx = threadIdx.x + q * kThreads, rr = idx >> 4, m = idx & 15, r = rr - kPad;
+    GRec<ST> g;
+    g.c = (ST)1; g.s = (ST)0; g.ic = (ST)1; g.ss = (ST)0;
+    if (r >= 0 && r < rows && m < kc) {
+      const GRec<ST>* src = T + (p + r) * kKP + m;
+      g.c = __hip_atomic_load(&src->c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      g.s = __hip_atomic_load(&src->s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      g.ic = __hip_atomic_load(&src->ic, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      g.ss = __hip_atomic_load(&src->ss, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    rg.g[q] = g;
+  }
+}
+
+template <typename ST>
+__device__ __forceinline__ void store_record_coherent(GRec<ST>* dst, const GRec<ST>& g) {
+  __hip_atomic_store(&dst->c, g.c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&dst->s, g.s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&dst->ic, g.ic, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&dst->ss, g.ss, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Apply the records in sh.R (rows [pa, pa + 64)) to columns [j0, j0 + ncols)
 // of the tile staged in sh.A, with this thread's V values w.  HEAD: V of
 // those columns goes to sh.Hb parity 1 (the chain's initial values);
@@ -212,23 +248,26 @@ __device__ __forceinline__ void tile_stage(SbLds& sh, const TileRegs<ST>& tr) {
 template <bool HEAD, int SG, typename ST, int KCF>
 __device__ __forceinline__ void apply_tile(SbLds& sh, ST* __restrict__ L, int64_t ldl,
                                            ST* __restrict__ W, int64_t ldw, int kc_,
-                                           int64_t pa, int64_t j0, int ncols, const ST (&w0)[4]) {
+                                           int64_t pa, int64_t j0, int ncols,
+                                           const ST (&w0)[kColsPerLane]) {
+  constexpr int NQ = kColsPerLane;
   const int kc = KCF ? KCF : kc_;
   const int tid = threadIdx.x;
-  const int g = tid & 15, grp = tid >> 4;  // lane g of group grp: columns grp + 16 q
-  ST w[4];
+  const int g = tid & 15, grp = tid >> 4;  // lane g of group grp: columns grp + 32 q
+  ST w[NQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) w[q] = w0[q];
+  for (int q = 0; q < NQ; ++q) w[q] = w0[q];
   // xin: lane 0 of a group takes row s of the tile, lane g > 0 the value
-  // lane g-1 produced at sub-step s-1 (the DPP shift's fill is the next row).
-  // The record and the tile row of sub-step s+1 are read during sub-step s
-  // (a tile row is read before lane kc-1 overwrites it with its final value:
-  // row s+2 is read at sub-step s, final at sub-step s+1+kc).
-  ST xin[4], nxt[4];
+  // lane g-1 produced at sub-step s-1 (the DPP shift's fill is the next row,
+  // which only lane 0 reads).  The record and the tile row of sub-step s+1
+  // are read during sub-step s (a tile row is read before lane kc-1
+  // overwrites it with its final value: row s+2 is read at sub-step s,
+  // final at sub-step s+1+kc).
+  ST xin[NQ], nxt[NQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    xin[q] = (ST)sh.A[0][grp + 16 * q];
-    nxt[q] = (ST)sh.A[1][grp + 16 * q];
+  for (int q = 0; q < NQ; ++q) {
+    xin[q] = (ST)sh.A[0][grp + kGroups * q];
+    nxt[q] = (ST)sh.A[1][grp + kGroups * q];
   }
   const RotRec* rp = &sh.R[kPad - g][g];  // record of row s - g at rp[s * kKP]
   RotRec cf = rp[0];
@@ -236,23 +275,25 @@ __device__ __forceinline__ void apply_tile(SbLds& sh, ST* __restrict__ L, int64_
   for (int s = 0; s < S; ++s) {
     const int r = s - g;
     const RotRec cfn = rp[imin(s + 1, kBR + kKP - 1 + g) * kKP];  // row <= 79
-    const int rn2 = imin(s + 2, kBR - 1);
-    ST nxt2[4];
+    ST nxt2[NQ];
+    if (g == 0) {
+      const int rn2 = imin(s + 2, kBR - 1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) nxt2[q] = (ST)sh.A[rn2][grp + 16 * q];
+      for (int q = 0; q < NQ; ++q) nxt2[q] = (ST)sh.A[rn2][grp + kGroups * q];
+    }
     const ST c = (ST)cf.c, sn = (ST)cf.s, ic = (ST)cf.ic;
-    ST x[4];
+    ST x[NQ];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       x[q] = fma_t((ST)SG * sn, w[q], xin[q]) * ic;
       w[q] = fma_t(-sn, x[q], c * w[q]);
     }
     if (g == kc - 1 && r >= 0 && r < kBR) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sh.A[r][grp + 16 * q] = x[q];
+      for (int q = 0; q < NQ; ++q) sh.A[r][grp + kGroups * q] = x[q];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       xin[q] = sb_shr1(x[q], nxt[q]);
       nxt[q] = nxt2[q];
     }
@@ -265,14 +306,110 @@ __device__ __forceinline__ void apply_tile(SbLds& sh, ST* __restrict__ L, int64_
     if (c < ncols) L[(pa + r) * ldl + j0 + c] = (ST)sh.A[r][c];
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int c = grp + 16 * q;
+  for (int q = 0; q < NQ; ++q) {
+    const int c = grp + kGroups * q;
     if (HEAD) {
       if (g < kc) sh.Hb[g][1][c] = (double)w[q];
     } else {
       if (c < ncols && g < kc) W[(j0 + c) * ldw + g] = w[q];
     }
   }
+}
+
+// ------------------------------------------------------------------ head
+// Head workgroups of the launch for block c apply blocks c-1 and c to the
+// columns of block c+1, 8 columns each, so that the next launch's chain
+// finds those columns ready.  Block c-1's records are known at launch;
+// block c's are published by this launch's chain workgroup (flag).
+constexpr int kHeadCols = 8;
+constexpr int kSpinLimit = 1 << 24;
+// s_waitcnt immediate (gfx9 encoding): vector memory count 0, export and LDS
+// counts left alone
+constexpr int kWaitVmem = 0x0F70;
+
+// Apply sh.R to columns [coff, coff + 8) of sh.A with this lane's V value w;
+// threads 0..127 (lane g of column group tid / 16) work, the others idle.
+template <int SG, typename ST, int KCF>
+__device__ __forceinline__ void narrow_apply(SbLds& sh, int kc_, int coff, ST& w) {
+  const int kc = KCF ? KCF : kc_;
+  const int tid = threadIdx.x;
+  if (tid >= 16 * kHeadCols) return;
+  const int g = tid & 15, c = coff + (tid >> 4);
+  ST xin = (ST)sh.A[0][c], nxt = (ST)sh.A[1][c];
+  const RotRec* rp = &sh.R[kPad - g][g];  // record of row s - g at rp[s * kKP]
+  RotRec cf = rp[0];
+  const int S = kBR + kc - 1;
+  for (int s = 0; s < S; ++s) {
+    const int r = s - g;
+    const RotRec cfn = rp[imin(s + 1, kBR + kKP - 1 + g) * kKP];  // row <= 79
+    const ST nxt2 = (ST)sh.A[imin(s + 2, kBR - 1)][c];
+    const ST cc = (ST)cf.c, sn = (ST)cf.s, ic = (ST)cf.ic;
+    const ST x = fma_t((ST)SG * sn, w, xin) * ic;
+    w = fma_t(-sn, x, cc * w);
+    if (g == kc - 1 && r >= 0 && r < kBR) sh.A[r][c] = x;
+    xin = sb_shr1(x, nxt);
+    nxt = nxt2;
+    cf = cfn;
+  }
+}
+
+template <int SG, typename ST, int KCF>
+__device__ __forceinline__ void head_wg(SbLds& sh, ST* __restrict__ L, int64_t ldl,
+                                        ST* __restrict__ W, int64_t ldw, int kc_, int64_t kfull,
+                                        int64_t m0, int64_t pa, int64_t pc, int64_t j0, int ncols,
+                                        GRec<ST>* __restrict__ T, int32_t* flag,
+                                        int64_t* __restrict__ info,
+                                        int64_t* __restrict__ stop_row, int64_t lim) {
+  const int kc = KCF ? KCF : kc_;
+  const int tid = threadIdx.x;
+  const bool ph1 = pa >= 0 && pa < lim;  // block c-1 (rows before a failure)
+  const bool ph2 = pc < lim;             // block c, once the chain has published it
+  RecRegs<ST> rg;
+  records_issue(rg, T, pa, ph1 ? (lim - pa < kBR ? (int)(lim - pa) : kBR) : 0, kc);
+  const int r = tid >> 3, c = tid & 7;  // one element of each 64 x 8 tile per thread
+  const ST a1 = (ph1 && c < ncols) ? L[(pa + r) * ldl + j0 + c] : (ST)0;
+  const ST a2 = (ph2 && c < ncols) ? L[(pc + r) * ldl + j0 + c] : (ST)0;
+  const int g = tid & 15, col = tid >> 4;
+  const bool wv = tid < 16 * kHeadCols && col < ncols && g < kc;
+  ST w = wv ? W[(j0 + col) * ldw + g] : (ST)0;
+  records_stage(sh, rg);
+  sh.A[r][c] = (double)a1;
+  sh.A[r][kHeadCols + c] = (double)a2;
+  __syncthreads();
+  if (ph1) narrow_apply<SG, ST, KCF>(sh, kc, 0, w);
+  bool ok2 = false;
+  if (ph2) {
+    if (tid == 0) {
+      int64_t got = -1;
+      for (int it = 0; it < kSpinLimit; ++it) {
+        // relaxed polling: the records are read with coherent loads below,
+        // so no cache invalidation is needed
+        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          got = __hip_atomic_load(stop_row, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (got < 0)  // the chain never published: report instead of waiting forever
+        atomicMin((unsigned long long*)info,
+                  (unsigned long long)info_key(pc * kfull + m0, kCodeTimeout));
+      sh.lim = got;
+    }
+    __syncthreads();  // also ends phase 1 (sh.R is rewritten below)
+    const int64_t lim2 = sh.lim;
+    ok2 = lim2 > pc;
+    if (ok2) {
+      RecRegs<ST> rg2;
+      records_issue_coherent(rg2, T, pc, lim2 - pc < kBR ? (int)(lim2 - pc) : kBR, kc);
+      records_stage(sh, rg2);
+    }
+    __syncthreads();
+    if (ok2) narrow_apply<SG, ST, KCF>(sh, kc, kHeadCols, w);
+  }
+  __syncthreads();
+  if (ph1 && c < ncols) L[(pa + r) * ldl + j0 + c] = (ST)sh.A[r][c];
+  if (ok2 && c < ncols) L[(pc + r) * ldl + j0 + c] = (ST)sh.A[r][kHeadCols + c];
+  if (wv) W[(j0 + col) * ldw + g] = w;
 }
 
 // ------------------------------------------------------------------ chain
@@ -397,7 +534,7 @@ __device__ __forceinline__ void helper_step(SbLds& sh, double (&st)[kSt], int t,
       if (m == kc - 1) sh.Lh[imin(t - 1 - m + kPad, kPad + kBR - 1)][jj] = x;
     }
   }
-  if (H < 2) sh.X[H < 2 ? H : 0][t & 1][jj] = st[2 * CNT - 1];
+  if (H < 5) sh.X[H < 5 ? H : 0][t & 1][jj] = st[2 * CNT - 1];
   if (H == 0) st[2 * CNT] = sh.Lb[imin(t, kBR - 1)][jj];
 }
 
@@ -425,25 +562,33 @@ __device__ __forceinline__ void helper_steps(SbLds& sh, int nsteps, int lane, in
 }
 
 // Workgroup 0: head tile, then the chain of block [pc, pc + bbc).
-template <int SG, typename ST, int KCF>
+// SPLIT: block c-1 has already been applied to block c's columns by the
+// head workgroups of the previous launch; publish the records (coherent
+// stores, then the flag) for this launch's head workgroups.
+template <int SG, typename ST, int KCF, bool SPLIT>
 __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t ldl,
                                          ST* __restrict__ W, int64_t ldw, int kc_,
                                          int64_t kfull, int64_t m0, int64_t pc, int bbc,
-                                         int64_t pa, GRec<ST>* __restrict__ T,
+                                         int64_t pa, GRec<ST>* __restrict__ T, int32_t* flag,
                                          int64_t* __restrict__ info,
                                          int64_t* __restrict__ stop_row, int64_t lim) {
   const int kc = KCF ? KCF : kc_;
   const int tid = threadIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const bool head = pa >= 0 && pa < lim;
+  const bool head = !SPLIT && pa >= 0 && pa < lim;
   const int hrows = head ? (lim - pa < kBR ? (int)(lim - pa) : kBR) : 0;
   const bool chain = pc < lim;  // else a failure in block b-1: finish its rows only
+  if (SPLIT && !chain) {
+    if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
   // issue every global load, then stage them in LDS
   RecRegs<ST> rg;
   records_issue(rg, T, pa, hrows, kc);  // all identity without a head tile
   TileRegs<ST> tr;
   if (head) tile_issue(tr, L, ldl, W, ldw, kc, pa, pc, bbc);
-  ST lt[kTilePerThread], wh[4];
+  constexpr int kHbPerThread = kBR * kKP / kThreads;  // 2
+  ST lt[kTilePerThread], wh[kHbPerThread];
   if (chain) {
 #pragma unroll
     for (int q = 0; q < kTilePerThread; ++q) {
@@ -452,7 +597,7 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
     }
     if (!head) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < kHbPerThread; ++q) {
         const int idx = tid + q * kThreads, c = idx >> 4, g = idx & 15;
         wh[q] = (g < kc && c < bbc) ? W[(pc + c) * ldw + g] : (ST)0;
       }
@@ -468,7 +613,7 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
     }
     if (!head) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < kHbPerThread; ++q) {
         const int idx = tid + q * kThreads;
         sh.Hb[idx & 15][1][idx >> 4] = (double)wh[q];
       }
@@ -482,7 +627,7 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
   for (int idx = tid; idx < kRRows * kKP; idx += kThreads) {
     if ((idx >> 4) >= kPad) sh.R[idx >> 4][idx & 15] = identity_rec();
   }
-  for (int idx = tid; idx < 2 * kBR; idx += kThreads) sh.X[idx >> 6][1][idx & 63] = 0.0;
+  for (int idx = tid; idx < 5 * kBR; idx += kThreads) sh.X[idx >> 6][1][idx & 63] = 0.0;
   if (tid == 0) sh.fail = 0x7fffffff;
   if (tid < kRRows) {
     const int r = tid < kBR ? tid : kBR - 1;
@@ -510,12 +655,21 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
     chain_steps<true, SG>(sh, st, 0, s0, lane, kc, bbc);
     chain_steps<false, SG>(sh, st, s0, s1, lane, kc, bbc);
     chain_steps<true, SG>(sh, st, s1, nsteps, lane, kc, bbc);
+  } else if (wv == 4) {
+    // shares its SIMD with wave 0: passes the same barriers and nothing else
+    for (int t = 0; t <= nsteps; ++t) __syncthreads();
   } else if (wv == 1) {
-    helper_steps<0, 0, 6, SG, KCF>(sh, nsteps, lane, kc);
+    helper_steps<0, 0, 3, SG, KCF>(sh, nsteps, lane, kc);
   } else if (wv == 2) {
-    helper_steps<1, 6, 5, SG, KCF>(sh, nsteps, lane, kc);
+    helper_steps<1, 3, 3, SG, KCF>(sh, nsteps, lane, kc);
+  } else if (wv == 3) {
+    helper_steps<2, 6, 3, SG, KCF>(sh, nsteps, lane, kc);
+  } else if (wv == 5) {
+    helper_steps<3, 9, 3, SG, KCF>(sh, nsteps, lane, kc);
+  } else if (wv == 6) {
+    helper_steps<4, 12, 2, SG, KCF>(sh, nsteps, lane, kc);
   } else {
-    helper_steps<2, 11, 5, SG, KCF>(sh, nsteps, lane, kc);
+    helper_steps<5, 14, 2, SG, KCF>(sh, nsteps, lane, kc);
   }
   // The first failing Compute of the block in (row, column) order.  A
   // Compute fails iff its radicand is not > 0 (then y, w and c are NaN) or,
@@ -557,32 +711,50 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
       const RotRec& rec = sh.R[r + kPad][m];
       GRec<ST> g;
       g.c = (ST)rec.c; g.s = (ST)rec.s; g.ic = (ST)rec.ic; g.ss = (ST)rec.ss;
-      T[(pc + r) * kKP + m] = g;
+      if (SPLIT) store_record_coherent(T + (pc + r) * kKP + m, g);
+      else T[(pc + r) * kKP + m] = g;
     }
+  }
+  if (SPLIT) {
+    // The records (and the failure row) are device-coherent stores; each
+    // wave waits until its own have been performed, then one coherent store
+    // raises the flag.  (A release fence would also write back everything
+    // else this XCD's L2 holds, which costs microseconds here.)
+    __builtin_amdgcn_s_waitcnt(kWaitVmem);
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// One workgroup's share of the launch for block [pc, pc + bbc) of one factor:
-// wg == 0 runs the chain, wg >= 1 applies block [pa, pa + 64) to the
-// 64-column tile wg - 1 right of the block.
-template <int SG, typename ST, int KCF>
+// One workgroup's share of the launch for block [pc, pc + bbc) of one factor.
+// wg == 0 runs the chain.  SPLIT: wg in [1, H] is head workgroup wg - 1
+// (columns of block c+1, kHeadCols each), the rest apply block [pa, pa+64)
+// to the 64-column tiles right of block c+1; otherwise wg >= 1 applies it to
+// the tiles right of block c (the chain workgroup does the head tile).
+template <int SG, typename ST, int KCF, bool SPLIT>
 __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_t ldl,
                                            ST* __restrict__ W, int64_t ldw, int kc,
                                            int64_t kfull, int64_t m0, int64_t n, int64_t pc,
                                            int bbc, int64_t pa, GRec<ST>* __restrict__ T,
                                            int64_t* __restrict__ info,
-                                           int64_t* __restrict__ stop_row, int wg) {
+                                           int64_t* __restrict__ stop_row, int wg, int H,
+                                           int bbc1, int32_t* flag) {
   // one read of the failure row per workgroup, so that every wave takes the same path
   if (threadIdx.x == 0)
     sh.lim = __hip_atomic_load(stop_row, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   const int64_t lim = sh.lim;
   if (wg == 0) {
-    chain_wg<SG, ST, KCF>(sh, L, ldl, W, ldw, kc, kfull, m0, pc, bbc, pa, T, info, stop_row,
-                          lim);
+    chain_wg<SG, ST, KCF, SPLIT>(sh, L, ldl, W, ldw, kc, kfull, m0, pc, bbc, pa, T, flag, info,
+                                 stop_row, lim);
+  } else if (SPLIT && wg <= H) {
+    const int h = wg - 1;
+    const int nc = bbc1 - h * kHeadCols < kHeadCols ? bbc1 - h * kHeadCols : kHeadCols;
+    head_wg<SG, ST, KCF>(sh, L, ldl, W, ldw, kc, kfull, m0, pa, pc,
+                         pc + bbc + (int64_t)h * kHeadCols, nc, T, flag, info, stop_row, lim);
   } else {
     if (pa < 0 || pa >= lim) return;
-    const int64_t j0 = pc + bbc + (int64_t)(wg - 1) * kBR;
+    const int64_t j0 = pc + bbc + (SPLIT ? bbc1 : 0) + (int64_t)(wg - 1 - (SPLIT ? H : 0)) * kBR;
     const int ncols = n - j0 < kBR ? (int)(n - j0) : kBR;
     RecRegs<ST> rg;
     records_issue(rg, T, pa, lim - pa < kBR ? (int)(lim - pa) : kBR, kc);
@@ -599,10 +771,11 @@ template <int SG, typename ST, int KCF>
 __global__ __launch_bounds__(kThreads) void k_sb_block(
     ST* __restrict__ L, int64_t ldl, ST* __restrict__ W, int64_t ldw, int kc, int64_t kfull,
     int64_t m0, int64_t n, int64_t pc, int bbc, int64_t pa, GRec<ST>* __restrict__ T,
-    int64_t* __restrict__ info, int64_t* __restrict__ stop_row) {
+    int64_t* __restrict__ info, int64_t* __restrict__ stop_row, int H, int bbc1,
+    int32_t* flag) {
   __shared__ SbLds sh;
-  block_work<SG, ST, KCF>(sh, L, ldl, W, ldw, kc, kfull, m0, n, pc, bbc, pa, T, info,
-                          stop_row, (int)blockIdx.x);
+  block_work<SG, ST, KCF, true>(sh, L, ldl, W, ldw, kc, kfull, m0, n, pc, bbc, pa, T, info,
+                                stop_row, (int)blockIdx.x, H, bbc1, flag);
 }
 
 // Batched form: the launch of step s holds, for every factor with more than
@@ -632,21 +805,21 @@ __global__ __launch_bounds__(kThreads) void k_sb_batch(const BatchFactor* __rest
     double* W = (double*)F.W + E.m0;
     GRec<double>* T = (GRec<double>*)F.T;
     if (F.sigma > 0)
-      block_work<1, double, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
-                            F.info, F.stop, wg);
+      block_work<1, double, 0, false>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+                            F.info, F.stop, wg, 0, 0, nullptr);
     else
-      block_work<-1, double, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
-                             F.info, F.stop, wg);
+      block_work<-1, double, 0, false>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+                             F.info, F.stop, wg, 0, 0, nullptr);
   } else {
     float* L = (float*)F.L;
     float* W = (float*)F.W + E.m0;
     GRec<float>* T = (GRec<float>*)F.T;
     if (F.sigma > 0)
-      block_work<1, float, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
-                           F.info, F.stop, wg);
+      block_work<1, float, 0, false>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+                           F.info, F.stop, wg, 0, 0, nullptr);
     else
-      block_work<-1, float, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
-                            F.info, F.stop, wg);
+      block_work<-1, float, 0, false>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+                            F.info, F.stop, wg, 0, 0, nullptr);
   }
 }
 
@@ -668,21 +841,26 @@ __global__ void k_prepare_batch(const BatchFactor* __restrict__ fac) {
 
 template <typename ST>
 hipError_t run_sysblk_t(hipStream_t st, ST* L, int64_t n, int64_t ldl, ST* W, int64_t k, int sg,
-                        void* Tws, int64_t* info, int64_t* stop) {
+                        void* Tws, int64_t* info, int64_t* stop, int32_t* flags) {
   GRec<ST>* R = reinterpret_cast<GRec<ST>*>(Tws);
+  const int64_t nb = (n + kBR - 1) / kBR;
   for (int64_t m0 = 0; m0 < k; m0 += kKP) {
     const int kc = (int)((k - m0) < kKP ? (k - m0) : kKP);
     ST* Wc = W + m0;
     for (int64_t pc = 0; pc < n; pc += kBR) {
       const int bbc = (int)((n - pc) < kBR ? (n - pc) : kBR);
       const int64_t pa = pc - kBR;  // previous block (always full), or < 0
-      const int64_t rest = n - (pc + bbc);
-      const unsigned grid = 1u + (pa >= 0 ? (unsigned)((rest + kBR - 1) / kBR) : 0u);
+      const int bbc1 = (int)((n - pc - bbc) < kBR ? (n - pc - bbc) : kBR);  // next block's rows
+      const int H = (bbc1 + kHeadCols - 1) / kHeadCols;
+      const int64_t rest = n - (pc + bbc + bbc1);
+      const unsigned grid =
+          1u + (unsigned)H + (pa >= 0 ? (unsigned)((rest + kBR - 1) / kBR) : 0u);
+      int32_t* flag = flags + (m0 / kKP) * nb + pc / kBR;
       // full passes (16 columns of V) use a variant specialised on that width
       auto kern = sg > 0 ? (kc == kKP ? k_sb_block<1, ST, kKP> : k_sb_block<1, ST, 0>)
                          : (kc == kKP ? k_sb_block<-1, ST, kKP> : k_sb_block<-1, ST, 0>);
       hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, L, ldl, Wc, k, kc, k, m0, n, pc,
-                         bbc, pa, R, info, stop);
+                         bbc, pa, R, info, stop, H, bbc1, flag);
     }
   }
   return hipGetLastError();
@@ -709,16 +887,16 @@ hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t co
 // Fast blocked schedule: V columns in passes of 16, one launch per block of
 // 64 rows.  W is the private copy of V (row stride k); T holds n x 16 records.
 hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
-                      double sg, Coef* T, int64_t* info, int64_t* stop) {
-  return run_sysblk_t<double>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop);
+                      double sg, Coef* T, int64_t* info, int64_t* stop, int32_t* flags) {
+  return run_sysblk_t<double>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, flags);
 }
 
 // The same schedule with L, V and the records stored in FP32: the rows of a
 // block (Compute and the Apply inside the block) run in FP64 from the FP32
 // values, the Apply to other blocks' columns runs in FP32.
 hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, float* W, int64_t k,
-                          double sg, void* T, int64_t* info, int64_t* stop) {
-  return run_sysblk_t<float>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop);
+                          double sg, void* T, int64_t* info, int64_t* stop, int32_t* flags) {
+  return run_sysblk_t<float>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, flags);
 }
 
 }  // namespace chm
