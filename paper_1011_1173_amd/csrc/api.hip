@@ -36,8 +36,8 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 //   [0, 768)         control words: the first failing row (int64) at 0
 //   W                n*k private copy of V
 //   T                n*max(16, min(k, 64)) rotation records of 32 bytes
-//   F                one int32 per (16-column pass, 64-row block): "the
-//                    block's records are in T" flags of the fast schedule
+//   F                one int32 per 16-column pass: the ticket counter of
+//                    that pass's launch in the fast schedule
 struct WsLayout {
   size_t ctrl = 0, w = 0, t = 0, f = 0, total = 0;
   int64_t nflags = 0;
@@ -58,7 +58,7 @@ bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out) {
   int64_t kp = k < kKPass ? k : kKPass;
   if (kp < 16) kp = 16;
   L.f = L.t + align_up((size_t)(n * kp) * sizeof(Coef));
-  L.nflags = ((n + 63) / 64) * ((k + 15) / 16);
+  L.nflags = (k + 15) / 16;
   L.total = L.f + align_up((size_t)L.nflags * sizeof(int32_t));
   *out = L;
   return true;

@@ -105,6 +105,8 @@ struct SbLds {
   Fill fl[kRRows];           // by step; steps with t + 1 >= bbc unused
   int64_t lim;              // first failing row known at launch
   int fail;                 // first failing (row * 16 + column) of the block
+  int tk;                   // owner schedule: this workgroup's ticket
+  int tmo;                  // owner schedule: a wait ran out of time
 };
 
 __device__ __forceinline__ double sb_shr1(double x, double fill) {
@@ -182,16 +184,22 @@ struct TileRegs {
 };
 
 template <typename ST>
-__device__ __forceinline__ void tile_issue(TileRegs<ST>& tr, const ST* __restrict__ L, int64_t ldl,
-                                           const ST* __restrict__ W, int64_t ldw, int kc,
-                                           int64_t pa, int64_t j0, int ncols) {
+__device__ __forceinline__ void tile_issue_a(TileRegs<ST>& tr, const ST* __restrict__ L,
+                                             int64_t ldl, int64_t pa, int64_t j0, int ncols) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int q = 0; q < kTilePerThread; ++q) {
     const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
     tr.a[q] = c < ncols ? L[(pa + r) * ldl + j0 + c] : (ST)0;
   }
-  const int g = tid & 15, grp = tid >> 4;
+}
+
+template <typename ST>
+__device__ __forceinline__ void tile_issue(TileRegs<ST>& tr, const ST* __restrict__ L, int64_t ldl,
+                                           const ST* __restrict__ W, int64_t ldw, int kc,
+                                           int64_t pa, int64_t j0, int ncols) {
+  tile_issue_a(tr, L, ldl, pa, j0, ncols);
+  const int g = threadIdx.x & 15, grp = threadIdx.x >> 4;
 #pragma unroll
   for (int q = 0; q < kColsPerLane; ++q) {
     const int c = grp + kGroups * q;
@@ -208,35 +216,37 @@ __device__ __forceinline__ void tile_stage(SbLds& sh, const TileRegs<ST>& tr) {
   }
 }
 
-// Records published by the chain workgroup of the same launch are written
-// and read with device-coherent (agent-scope) accesses, so that they are
-// seen across the GPU's separate L2 caches.
+// Records passed between the workgroups of one launch (the owner schedule
+// below) are written and read with device-scope accesses, so that they are
+// seen across the GPU's separate L2 caches.  A record field holding kEmpty (a
+// signalling NaN, which no arithmetic result is) has not been written yet:
+// the workspace is filled with it before the launch, so the data is its own
+// "ready" flag and no fence or flag store is needed.
 template <typename ST>
-__device__ __forceinline__ void records_issue_coherent(RecRegs<ST>& rg,
-                                                       const GRec<ST>* __restrict__ T, int64_t p,
-                                                       int rows, int kc) {
-#pragma unroll
-  for (int q = 0; q < kRecPerThread; ++q) {
-    const int idx = threadIdx.x + q * kThreads, rr = idx >> 4, m = idx & 15, r = rr - kPad;
-    GRec<ST> g;
-    g.c = (ST)1; g.s = (ST)0; g.ic = (ST)1; g.ss = (ST)0;
-    if (r >= 0 && r < rows && m < kc) {
-      const GRec<ST>* src = T + (p + r) * kKP + m;
-      g.c = __hip_atomic_load(&src->c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      g.s = __hip_atomic_load(&src->s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      g.ic = __hip_atomic_load(&src->ic, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      g.ss = __hip_atomic_load(&src->ss, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    rg.g[q] = g;
-  }
+struct RecBits;
+template <>
+struct RecBits<double> {
+  using U = uint64_t;
+  static constexpr U kEmpty = 0x7FF4A5A5A5A5A5A5ull;
+};
+template <>
+struct RecBits<float> {
+  using U = uint32_t;
+  static constexpr U kEmpty = 0x7FA5A5A5u;
+};
+
+template <typename ST>
+__device__ __forceinline__ typename RecBits<ST>::U load_bits(const ST* p) {
+  using U = typename RecBits<ST>::U;
+  return __hip_atomic_load(reinterpret_cast<U*>(const_cast<ST*>(p)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename ST>
-__device__ __forceinline__ void store_record_coherent(GRec<ST>* dst, const GRec<ST>& g) {
-  __hip_atomic_store(&dst->c, g.c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&dst->s, g.s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&dst->ic, g.ic, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&dst->ss, g.ss, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void publish_record(GRec<ST>* dst, const RotRec& r) {
+  __hip_atomic_store(&dst->c, (ST)r.c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&dst->s, (ST)r.s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&dst->ic, (ST)r.ic, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Apply the records in sh.R (rows [pa, pa + 64)) to columns [j0, j0 + ncols)
@@ -314,102 +324,6 @@ __device__ __forceinline__ void apply_tile(SbLds& sh, ST* __restrict__ L, int64_
       if (c < ncols && g < kc) W[(j0 + c) * ldw + g] = w[q];
     }
   }
-}
-
-// ------------------------------------------------------------------ head
-// Head workgroups of the launch for block c apply blocks c-1 and c to the
-// columns of block c+1, 8 columns each, so that the next launch's chain
-// finds those columns ready.  Block c-1's records are known at launch;
-// block c's are published by this launch's chain workgroup (flag).
-constexpr int kHeadCols = 8;
-constexpr int kSpinLimit = 1 << 24;
-// s_waitcnt immediate (gfx9 encoding): vector memory count 0, export and LDS
-// counts left alone
-constexpr int kWaitVmem = 0x0F70;
-
-// Apply sh.R to columns [coff, coff + 8) of sh.A with this lane's V value w;
-// threads 0..127 (lane g of column group tid / 16) work, the others idle.
-template <int SG, typename ST, int KCF>
-__device__ __forceinline__ void narrow_apply(SbLds& sh, int kc_, int coff, ST& w) {
-  const int kc = KCF ? KCF : kc_;
-  const int tid = threadIdx.x;
-  if (tid >= 16 * kHeadCols) return;
-  const int g = tid & 15, c = coff + (tid >> 4);
-  ST xin = (ST)sh.A[0][c], nxt = (ST)sh.A[1][c];
-  const RotRec* rp = &sh.R[kPad - g][g];  // record of row s - g at rp[s * kKP]
-  RotRec cf = rp[0];
-  const int S = kBR + kc - 1;
-  for (int s = 0; s < S; ++s) {
-    const int r = s - g;
-    const RotRec cfn = rp[imin(s + 1, kBR + kKP - 1 + g) * kKP];  // row <= 79
-    const ST nxt2 = (ST)sh.A[imin(s + 2, kBR - 1)][c];
-    const ST cc = (ST)cf.c, sn = (ST)cf.s, ic = (ST)cf.ic;
-    const ST x = fma_t((ST)SG * sn, w, xin) * ic;
-    w = fma_t(-sn, x, cc * w);
-    if (g == kc - 1 && r >= 0 && r < kBR) sh.A[r][c] = x;
-    xin = sb_shr1(x, nxt);
-    nxt = nxt2;
-    cf = cfn;
-  }
-}
-
-template <int SG, typename ST, int KCF>
-__device__ __forceinline__ void head_wg(SbLds& sh, ST* __restrict__ L, int64_t ldl,
-                                        ST* __restrict__ W, int64_t ldw, int kc_, int64_t kfull,
-                                        int64_t m0, int64_t pa, int64_t pc, int64_t j0, int ncols,
-                                        GRec<ST>* __restrict__ T, int32_t* flag,
-                                        int64_t* __restrict__ info,
-                                        int64_t* __restrict__ stop_row, int64_t lim) {
-  const int kc = KCF ? KCF : kc_;
-  const int tid = threadIdx.x;
-  const bool ph1 = pa >= 0 && pa < lim;  // block c-1 (rows before a failure)
-  const bool ph2 = pc < lim;             // block c, once the chain has published it
-  RecRegs<ST> rg;
-  records_issue(rg, T, pa, ph1 ? (lim - pa < kBR ? (int)(lim - pa) : kBR) : 0, kc);
-  const int r = tid >> 3, c = tid & 7;  // one element of each 64 x 8 tile per thread
-  const ST a1 = (ph1 && c < ncols) ? L[(pa + r) * ldl + j0 + c] : (ST)0;
-  const ST a2 = (ph2 && c < ncols) ? L[(pc + r) * ldl + j0 + c] : (ST)0;
-  const int g = tid & 15, col = tid >> 4;
-  const bool wv = tid < 16 * kHeadCols && col < ncols && g < kc;
-  ST w = wv ? W[(j0 + col) * ldw + g] : (ST)0;
-  records_stage(sh, rg);
-  sh.A[r][c] = (double)a1;
-  sh.A[r][kHeadCols + c] = (double)a2;
-  __syncthreads();
-  if (ph1) narrow_apply<SG, ST, KCF>(sh, kc, 0, w);
-  bool ok2 = false;
-  if (ph2) {
-    if (tid == 0) {
-      int64_t got = -1;
-      for (int it = 0; it < kSpinLimit; ++it) {
-        // relaxed polling: the records are read with coherent loads below,
-        // so no cache invalidation is needed
-        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-          got = __hip_atomic_load(stop_row, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
-      if (got < 0)  // the chain never published: report instead of waiting forever
-        atomicMin((unsigned long long*)info,
-                  (unsigned long long)info_key(pc * kfull + m0, kCodeTimeout));
-      sh.lim = got;
-    }
-    __syncthreads();  // also ends phase 1 (sh.R is rewritten below)
-    const int64_t lim2 = sh.lim;
-    ok2 = lim2 > pc;
-    if (ok2) {
-      RecRegs<ST> rg2;
-      records_issue_coherent(rg2, T, pc, lim2 - pc < kBR ? (int)(lim2 - pc) : kBR, kc);
-      records_stage(sh, rg2);
-    }
-    __syncthreads();
-    if (ok2) narrow_apply<SG, ST, KCF>(sh, kc, kHeadCols, w);
-  }
-  __syncthreads();
-  if (ph1 && c < ncols) L[(pa + r) * ldl + j0 + c] = (ST)sh.A[r][c];
-  if (ok2 && c < ncols) L[(pc + r) * ldl + j0 + c] = (ST)sh.A[r][kHeadCols + c];
-  if (wv) W[(j0 + col) * ldw + g] = w;
 }
 
 // ------------------------------------------------------------------ chain
@@ -561,27 +475,149 @@ __device__ __forceinline__ void helper_steps(SbLds& sh, int nsteps, int lane, in
   }
 }
 
-// Workgroup 0: head tile, then the chain of block [pc, pc + bbc).
-// SPLIT: block c-1 has already been applied to block c's columns by the
-// head workgroups of the previous launch; publish the records (coherent
-// stores, then the flag) for this launch's head workgroups.
-template <int SG, typename ST, int KCF, bool SPLIT>
+// LDS set-up of a chain (the block's triangle staged in sh.Lb): identity
+// records for the block's rows until wave 0 writes them, the helpers'
+// transfer rows cleared, and each row's diagonal and lane 0's inputs.
+__device__ __forceinline__ void chain_setup(SbLds& sh, int bbc) {
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kRRows * kKP; idx += kThreads) {
+    if ((idx >> 4) >= kPad) sh.R[idx >> 4][idx & 15] = identity_rec();
+  }
+  for (int idx = tid; idx < 5 * kBR; idx += kThreads) sh.X[idx >> 6][1][idx & 63] = 0.0;
+  if (tid == 0) sh.fail = 0x7fffffff;
+  if (tid < kRRows) {
+    const int r = tid < kBR ? tid : kBR - 1;
+    const double l = sh.Lb[r][r];
+    DiagPre d;
+    d.l = l;
+    d.t = l * l;
+    d.il = 1.0 / l;
+    d.pad = 0.0;
+    sh.dg[tid] = d;
+    // lane 0 at step t applies rows t-1 and t to column t+1
+    Fill f;
+    f.lo = (tid >= 1 && tid + 1 < bbc) ? sh.Lb[tid - 1][tid + 1] : 0.0;
+    f.hi = (tid + 1 < bbc) ? sh.Lb[tid][tid + 1] : 0.0;
+    sh.fl[tid] = f;
+  }
+}
+
+// Wave 4 (owner schedule): the records of rows [r0, r0 + 16) of block
+// [pc, pc + 64), complete in sh.R, go to T for the owners of later blocks.
+template <typename ST>
+__device__ __forceinline__ void publish_rows(SbLds& sh, GRec<ST>* __restrict__ T, int64_t pc,
+                                             int r0, int kc, int lane) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int e = lane + 64 * v, r = r0 + (e >> 4), m = e & 15;
+    if (m < kc) publish_record(T + (pc + r) * kKP + m, sh.R[r + kPad][m]);
+  }
+}
+
+// The step loops of the chain of block [pc, pc + bbc); sh is set up and V of
+// the block's columns is in sh.Hb parity 1.  pub (full blocks with a later
+// block only): wave 4 publishes the records 16 rows at a time as they
+// complete.  After barrier u of the loop (u = 0 .. nsteps) the rows up to
+// u - kc are complete: row i's last record is written at step i + kc - 1.
+template <int SG, typename ST, int KCF>
+__device__ __forceinline__ void chain_loops(SbLds& sh, int kc, int bbc, bool pub,
+                                            GRec<ST>* __restrict__ T, int64_t pc) {
+  const int tid = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  // steady steps [s0, s1): every lane m < kc has i >= 0 and i + 1 < bbc
+  const int nsteps = bbc + kc - 1;
+  const int s0 = kc - 1, s1 = imax(kc - 1, bbc - 1);
+  if (wv == 0) {
+    double st[kSt];
+    chain_init(sh, st, lane, bbc);
+    __syncthreads();
+    chain_steps<true, SG>(sh, st, 0, s0, lane, kc, bbc);
+    chain_steps<false, SG>(sh, st, s0, s1, lane, kc, bbc);
+    chain_steps<true, SG>(sh, st, s1, nsteps, lane, kc, bbc);
+  } else if (wv == 4) {
+    // shares its SIMD with wave 0: passes the same barriers and publishes
+    int q = 0;
+    for (int u = 0; u <= nsteps; ++u) {
+      __syncthreads();
+      if (pub && q < kBR / 16 && u == 16 * q + 15 + kc) {
+        publish_rows(sh, T, pc, 16 * q, kc, lane);
+        ++q;
+      }
+    }
+  } else if (wv == 1) {
+    helper_steps<0, 0, 3, SG, KCF>(sh, nsteps, lane, kc);
+  } else if (wv == 2) {
+    helper_steps<1, 3, 3, SG, KCF>(sh, nsteps, lane, kc);
+  } else if (wv == 3) {
+    helper_steps<2, 6, 3, SG, KCF>(sh, nsteps, lane, kc);
+  } else if (wv == 5) {
+    helper_steps<3, 9, 3, SG, KCF>(sh, nsteps, lane, kc);
+  } else if (wv == 6) {
+    helper_steps<4, 12, 2, SG, KCF>(sh, nsteps, lane, kc);
+  } else {
+    helper_steps<5, 14, 2, SG, KCF>(sh, nsteps, lane, kc);
+  }
+}
+
+// After the loops: the first failure of the block and the block's triangle.
+// A Compute fails iff its radicand is not > 0 (then y, w and c are NaN) or,
+// for column 0, the original diagonal is not > 0 (then c = w / L_ii is
+// negative, infinite or NaN); every later Compute of the same row or of a
+// later row may be garbage, none of an earlier row is.  So the failure is
+// the first record whose c is not a finite positive number.
+template <typename ST>
+__device__ __forceinline__ void chain_finish(SbLds& sh, ST* __restrict__ L, int64_t ldl, int kc,
+                                             int64_t kfull, int64_t m0, int64_t pc, int bbc,
+                                             int64_t* __restrict__ info,
+                                             int64_t* __restrict__ stop_row) {
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kBR * kKP; idx += kThreads) {
+    const int r = idx >> 4, m = idx & 15;
+    if (r < bbc && m < kc) {
+      const double c = sh.R[r + kPad][m].c;
+      if (!(c > 0.0 && c < __builtin_huge_val())) atomicMin(&sh.fail, idx);
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && sh.fail != 0x7fffffff) {
+    const int r = sh.fail >> 4, m = sh.fail & 15;
+    const int64_t code = (m == 0 && !(sh.dg[r].l > 0.0)) ? kCodeBadDiag : kCodeNotPD;
+    atomicMin((unsigned long long*)info,
+              (unsigned long long)info_key((pc + r) * kfull + m0 + m, code));
+    atomicMin((unsigned long long*)stop_row, (unsigned long long)(pc + r));
+  }
+  // diagonal and two superdiagonals from wave 0, the rest from the helper
+  // holding column kc - 1 of V
+  for (int idx = tid; idx < kBR * kBR; idx += kThreads) {
+    const int i = idx >> 6, j = idx & 63;
+    if (i < bbc && j < bbc && j >= i) {
+      double x;
+      if (j == i) x = sh.Lc[i + kPad].d;
+      else if (j == i + 1) x = sh.Lc[i + kPad].hi;
+      else if (j == i + 2) x = sh.Lc[i + 1 + kPad].lo;
+      else x = sh.Lh[i + kPad][j];
+      L[(pc + i) * ldl + pc + j] = (ST)x;
+    }
+  }
+}
+
+// ------------------------------------------------------- launch per block
+// Batched factors run one launch per step: workgroup 0 applies block b-1 to
+// the columns of block b (the head tile), then runs the chain of block b and
+// writes its records for the next launch; the other workgroups apply block
+// b-1 to the 64-column tiles right of block b.
+template <int SG, typename ST, int KCF>
 __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t ldl,
                                          ST* __restrict__ W, int64_t ldw, int kc_,
                                          int64_t kfull, int64_t m0, int64_t pc, int bbc,
-                                         int64_t pa, GRec<ST>* __restrict__ T, int32_t* flag,
+                                         int64_t pa, GRec<ST>* __restrict__ T,
                                          int64_t* __restrict__ info,
                                          int64_t* __restrict__ stop_row, int64_t lim) {
   const int kc = KCF ? KCF : kc_;
   const int tid = threadIdx.x;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const bool head = !SPLIT && pa >= 0 && pa < lim;
+  const bool head = pa >= 0 && pa < lim;
   const int hrows = head ? (lim - pa < kBR ? (int)(lim - pa) : kBR) : 0;
   const bool chain = pc < lim;  // else a failure in block b-1: finish its rows only
-  if (SPLIT && !chain) {
-    if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return;
-  }
   // issue every global load, then stage them in LDS
   RecRegs<ST> rg;
   records_issue(rg, T, pa, hrows, kc);  // all identity without a head tile
@@ -623,138 +659,42 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
   if (head) apply_tile<true, SG, ST, KCF>(sh, L, ldl, W, ldw, kc, pa, pc, bbc, tr.w);
   if (!chain) return;
   __syncthreads();
-  // identity records for this block's rows until wave 0 writes them
-  for (int idx = tid; idx < kRRows * kKP; idx += kThreads) {
-    if ((idx >> 4) >= kPad) sh.R[idx >> 4][idx & 15] = identity_rec();
-  }
-  for (int idx = tid; idx < 5 * kBR; idx += kThreads) sh.X[idx >> 6][1][idx & 63] = 0.0;
-  if (tid == 0) sh.fail = 0x7fffffff;
-  if (tid < kRRows) {
-    const int r = tid < kBR ? tid : kBR - 1;
-    const double l = sh.Lb[r][r];
-    DiagPre d;
-    d.l = l;
-    d.t = l * l;
-    d.il = 1.0 / l;
-    d.pad = 0.0;
-    sh.dg[tid] = d;
-    // lane 0 at step t applies rows t-1 and t to column t+1
-    Fill f;
-    f.lo = (tid >= 1 && tid + 1 < bbc) ? sh.Lb[tid - 1][tid + 1] : 0.0;
-    f.hi = (tid + 1 < bbc) ? sh.Lb[tid][tid + 1] : 0.0;
-    sh.fl[tid] = f;
-  }
+  chain_setup(sh, bbc);
   __syncthreads();
-  // steady steps [s0, s1): every lane m < kc has i >= 0 and i + 1 < bbc
-  const int nsteps = bbc + kc - 1;
-  const int s0 = kc - 1, s1 = imax(kc - 1, bbc - 1);
-  if (wv == 0) {
-    double st[kSt];
-    chain_init(sh, st, lane, bbc);
-    __syncthreads();
-    chain_steps<true, SG>(sh, st, 0, s0, lane, kc, bbc);
-    chain_steps<false, SG>(sh, st, s0, s1, lane, kc, bbc);
-    chain_steps<true, SG>(sh, st, s1, nsteps, lane, kc, bbc);
-  } else if (wv == 4) {
-    // shares its SIMD with wave 0: passes the same barriers and nothing else
-    for (int t = 0; t <= nsteps; ++t) __syncthreads();
-  } else if (wv == 1) {
-    helper_steps<0, 0, 3, SG, KCF>(sh, nsteps, lane, kc);
-  } else if (wv == 2) {
-    helper_steps<1, 3, 3, SG, KCF>(sh, nsteps, lane, kc);
-  } else if (wv == 3) {
-    helper_steps<2, 6, 3, SG, KCF>(sh, nsteps, lane, kc);
-  } else if (wv == 5) {
-    helper_steps<3, 9, 3, SG, KCF>(sh, nsteps, lane, kc);
-  } else if (wv == 6) {
-    helper_steps<4, 12, 2, SG, KCF>(sh, nsteps, lane, kc);
-  } else {
-    helper_steps<5, 14, 2, SG, KCF>(sh, nsteps, lane, kc);
-  }
-  // The first failing Compute of the block in (row, column) order.  A
-  // Compute fails iff its radicand is not > 0 (then y, w and c are NaN) or,
-  // for column 0, the original diagonal is not > 0 (then c = w / L_ii is
-  // negative, infinite or NaN); every later Compute of the same row or of a
-  // later row may be garbage, none of an earlier row is.  So the failure is
-  // the first record whose c is not a finite positive number.
-  for (int idx = tid; idx < kBR * kKP; idx += kThreads) {
-    const int r = idx >> 4, m = idx & 15;
-    if (r < bbc && m < kc) {
-      const double c = sh.R[r + kPad][m].c;
-      if (!(c > 0.0 && c < __builtin_huge_val())) atomicMin(&sh.fail, idx);
-    }
-  }
-  __syncthreads();
-  if (tid == 0 && sh.fail != 0x7fffffff) {
-    const int r = sh.fail >> 4, m = sh.fail & 15;
-    const int64_t code = (m == 0 && !(sh.dg[r].l > 0.0)) ? kCodeBadDiag : kCodeNotPD;
-    atomicMin((unsigned long long*)info,
-              (unsigned long long)info_key((pc + r) * kfull + m0 + m, code));
-    atomicMin((unsigned long long*)stop_row, (unsigned long long)(pc + r));
-  }
-  // the block's triangle (diagonal and two superdiagonals from wave 0, the
-  // rest from the helper holding column kc - 1 of V) and its records
-  for (int idx = tid; idx < kBR * kBR; idx += kThreads) {
-    const int i = idx >> 6, j = idx & 63;
-    if (i < bbc && j < bbc && j >= i) {
-      double x;
-      if (j == i) x = sh.Lc[i + kPad].d;
-      else if (j == i + 1) x = sh.Lc[i + kPad].hi;
-      else if (j == i + 2) x = sh.Lc[i + 1 + kPad].lo;
-      else x = sh.Lh[i + kPad][j];
-      L[(pc + i) * ldl + pc + j] = (ST)x;
-    }
-  }
+  chain_loops<SG, ST, KCF>(sh, kc, bbc, false, T, pc);
+  chain_finish(sh, L, ldl, kc, kfull, m0, pc, bbc, info, stop_row);
   for (int idx = tid; idx < kBR * kKP; idx += kThreads) {
     const int r = idx >> 4, m = idx & 15;
     if (r < bbc && m < kc) {
       const RotRec& rec = sh.R[r + kPad][m];
       GRec<ST> g;
       g.c = (ST)rec.c; g.s = (ST)rec.s; g.ic = (ST)rec.ic; g.ss = (ST)rec.ss;
-      if (SPLIT) store_record_coherent(T + (pc + r) * kKP + m, g);
-      else T[(pc + r) * kKP + m] = g;
+      T[(pc + r) * kKP + m] = g;
     }
-  }
-  if (SPLIT) {
-    // The records (and the failure row) are device-coherent stores; each
-    // wave waits until its own have been performed, then one coherent store
-    // raises the flag.  (A release fence would also write back everything
-    // else this XCD's L2 holds, which costs microseconds here.)
-    __builtin_amdgcn_s_waitcnt(kWaitVmem);
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// One workgroup's share of the launch for block [pc, pc + bbc) of one factor.
-// wg == 0 runs the chain.  SPLIT: wg in [1, H] is head workgroup wg - 1
-// (columns of block c+1, kHeadCols each), the rest apply block [pa, pa+64)
-// to the 64-column tiles right of block c+1; otherwise wg >= 1 applies it to
-// the tiles right of block c (the chain workgroup does the head tile).
-template <int SG, typename ST, int KCF, bool SPLIT>
+// One workgroup's share of the launch for block [pc, pc + bbc) of one factor:
+// wg == 0 runs the chain, wg >= 1 applies block [pa, pa + 64) to the tiles
+// right of block b.
+template <int SG, typename ST, int KCF>
 __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_t ldl,
                                            ST* __restrict__ W, int64_t ldw, int kc,
                                            int64_t kfull, int64_t m0, int64_t n, int64_t pc,
                                            int bbc, int64_t pa, GRec<ST>* __restrict__ T,
                                            int64_t* __restrict__ info,
-                                           int64_t* __restrict__ stop_row, int wg, int H,
-                                           int bbc1, int32_t* flag) {
+                                           int64_t* __restrict__ stop_row, int wg) {
   // one read of the failure row per workgroup, so that every wave takes the same path
   if (threadIdx.x == 0)
     sh.lim = __hip_atomic_load(stop_row, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   const int64_t lim = sh.lim;
   if (wg == 0) {
-    chain_wg<SG, ST, KCF, SPLIT>(sh, L, ldl, W, ldw, kc, kfull, m0, pc, bbc, pa, T, flag, info,
-                                 stop_row, lim);
-  } else if (SPLIT && wg <= H) {
-    const int h = wg - 1;
-    const int nc = bbc1 - h * kHeadCols < kHeadCols ? bbc1 - h * kHeadCols : kHeadCols;
-    head_wg<SG, ST, KCF>(sh, L, ldl, W, ldw, kc, kfull, m0, pa, pc,
-                         pc + bbc + (int64_t)h * kHeadCols, nc, T, flag, info, stop_row, lim);
+    chain_wg<SG, ST, KCF>(sh, L, ldl, W, ldw, kc, kfull, m0, pc, bbc, pa, T, info, stop_row,
+                          lim);
   } else {
     if (pa < 0 || pa >= lim) return;
-    const int64_t j0 = pc + bbc + (SPLIT ? bbc1 : 0) + (int64_t)(wg - 1 - (SPLIT ? H : 0)) * kBR;
+    const int64_t j0 = pc + bbc + (int64_t)(wg - 1) * kBR;
     const int ncols = n - j0 < kBR ? (int)(n - j0) : kBR;
     RecRegs<ST> rg;
     records_issue(rg, T, pa, lim - pa < kBR ? (int)(lim - pa) : kBR, kc);
@@ -767,15 +707,195 @@ __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_
   }
 }
 
+// ---------------------------------------------------------- owner schedule
+// One launch per pass of 16 columns of V.  The workgroup with ticket j (the
+// j-th to start) owns the columns of block j: it applies blocks 0 .. j-1 to
+// them in row order, each as its owner publishes it, keeping V of its
+// columns in registers, then runs the chain of block j itself and publishes
+// the block's records 16 rows at a time while the chain runs.  A workgroup
+// waits only for workgroups that started before it, so every wait ends; each
+// wait is still bounded: all of a workgroup's waits end kWaitTicks after it
+// started (then the launch reports kCodeTimeout and its results are void).
+constexpr int64_t kWaitTicks = 500000000;  // steady-counter ticks (5 s at 100 MHz)
+
+// Apply block [pb, pb + 64) to the owner's columns [j0, j0 + ncols) (tile
+// staged in sh.A; w: this thread's V values, lane g of group grp: columns
+// grp + 32 q, column g of V).  The records arrive 16 rows at a time; the
+// sub-steps that need rows of the next 16 wait for them.  Same operations,
+// in the same order, as apply_tile.
 template <int SG, typename ST, int KCF>
-__global__ __launch_bounds__(kThreads) void k_sb_block(
-    ST* __restrict__ L, int64_t ldl, ST* __restrict__ W, int64_t ldw, int kc, int64_t kfull,
-    int64_t m0, int64_t n, int64_t pc, int bbc, int64_t pa, GRec<ST>* __restrict__ T,
-    int64_t* __restrict__ info, int64_t* __restrict__ stop_row, int H, int bbc1,
-    int32_t* flag) {
+__device__ __forceinline__ void owner_apply(SbLds& sh, ST* __restrict__ L, int64_t ldl, int kc_,
+                                            int64_t pb, int64_t j0, int ncols,
+                                            ST (&w)[kColsPerLane],
+                                            const GRec<ST>* __restrict__ T, int64_t deadline) {
+  using U = typename RecBits<ST>::U;
+  constexpr U kE = RecBits<ST>::kEmpty;
+  constexpr int NQ = kColsPerLane;
+  const int kc = KCF ? KCF : kc_;
+  const int tid = threadIdx.x;
+  const int g = tid & 15, grp = tid >> 4;
+  // this thread's records: (row, column) = ((tid + 512 e) >> 4, tid & 15),
+  // e = 0, 1, so rows [16 q, 16 q + 16) are held by e = q / 2 of the threads
+  // with tid / 256 = q % 2
+  const int mr = tid & 15;
+  U rb[2][3];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int r = (tid + kThreads * e) >> 4;
+    if (mr < kc) {
+      const GRec<ST>* src = T + (pb + r) * kKP + mr;
+      rb[e][0] = load_bits(&src->c);
+      rb[e][1] = load_bits(&src->s);
+      rb[e][2] = load_bits(&src->ic);
+    }
+  }
+  ST xin[NQ], nxt[NQ];
+  const RotRec* rp = &sh.R[kPad - g][g];  // record of row s - g at rp[s * kKP]
+  const int S = kBR + kc - 1;
+#pragma unroll
+  for (int q = 0; q < kBR / 16; ++q) {
+    const int e = q >> 1;
+    if ((tid >> 8) == (q & 1) && mr < kc) {
+      const int r = (tid + kThreads * e) >> 4;
+      U c = rb[e][0], s = rb[e][1], ic = rb[e][2];
+      if (c == kE || s == kE || ic == kE) {
+        const GRec<ST>* src = T + (pb + r) * kKP + mr;
+        do {
+          __builtin_amdgcn_s_sleep(1);
+          c = load_bits(&src->c);
+          s = load_bits(&src->s);
+          ic = load_bits(&src->ic);
+          if (wall_clock64() > deadline) {
+            sh.tmo = 1;
+            break;
+          }
+        } while (c == kE || s == kE || ic == kE);
+      }
+      RotRec rec;
+      rec.c = (double)__builtin_bit_cast(ST, c);
+      rec.s = (double)__builtin_bit_cast(ST, s);
+      rec.ic = (double)__builtin_bit_cast(ST, ic);
+      rec.ss = 0.0;
+      sh.R[kPad + r][mr] = rec;
+    }
+    __syncthreads();
+    if (q == 0) {
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) {
+        xin[u] = (ST)sh.A[0][grp + kGroups * u];
+        nxt[u] = (ST)sh.A[1][grp + kGroups * u];
+      }
+    }
+    const int s_end = q == kBR / 16 - 1 ? S : 16 * q + 16;
+    RotRec cf = rp[16 * q * kKP];
+    for (int s = 16 * q; s < s_end; ++s) {
+      const int r = s - g;
+      const RotRec cfn = rp[imin(s + 1, kBR + kKP - 1 + g) * kKP];  // row <= 79
+      ST nxt2[NQ];
+      if (g == 0) {
+        const int rn2 = imin(s + 2, kBR - 1);
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) nxt2[u] = (ST)sh.A[rn2][grp + kGroups * u];
+      }
+      const ST c = (ST)cf.c, sn = (ST)cf.s, ic = (ST)cf.ic;
+      ST x[NQ];
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) {
+        x[u] = fma_t((ST)SG * sn, w[u], xin[u]) * ic;
+        w[u] = fma_t(-sn, x[u], c * w[u]);
+      }
+      if (g == kc - 1 && r >= 0 && r < kBR) {
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) sh.A[r][grp + kGroups * u] = x[u];
+      }
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) {
+        xin[u] = sb_shr1(x[u], nxt[u]);
+        nxt[u] = nxt2[u];
+      }
+      cf = cfn;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kTilePerThread; ++q) {
+    const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
+    if (c < ncols) L[(pb + r) * ldl + j0 + c] = (ST)sh.A[r][c];
+  }
+}
+
+template <int SG, typename ST, int KCF>
+__global__ __launch_bounds__(kThreads) void k_sb_owner(
+    ST* __restrict__ L, int64_t ldl, const ST* __restrict__ W, int64_t ldw, int kc_,
+    int64_t kfull, int64_t m0, int64_t n, GRec<ST>* __restrict__ T,
+    int64_t* __restrict__ info, int64_t* __restrict__ stop_row, int32_t* __restrict__ ticket) {
   __shared__ SbLds sh;
-  block_work<SG, ST, KCF, true>(sh, L, ldl, W, ldw, kc, kfull, m0, n, pc, bbc, pa, T, info,
-                                stop_row, (int)blockIdx.x, H, bbc1, flag);
+  const int kc = KCF ? KCF : kc_;
+  const int tid = threadIdx.x;
+  const int64_t deadline = wall_clock64() + kWaitTicks;
+  if (tid == 0) {
+    sh.tk = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sh.tmo = 0;
+  }
+  __syncthreads();
+  const int j = sh.tk;
+  const int64_t pj = (int64_t)j * kBR;
+  const int bbc = n - pj < kBR ? (int)(n - pj) : kBR;
+  // every global input of the workgroup is issued before anything is staged:
+  // the block's triangle, V of its columns and the first tile
+  ST lt[kTilePerThread];
+#pragma unroll
+  for (int q = 0; q < kTilePerThread; ++q) {
+    const int idx = tid + q * kThreads, i = idx >> 6, c = idx & 63;
+    lt[q] = (i < bbc && c < bbc && c >= i) ? L[(pj + i) * ldl + pj + c] : (ST)0;
+  }
+  const int g = tid & 15, grp = tid >> 4;
+  ST w[kColsPerLane];
+#pragma unroll
+  for (int q = 0; q < kColsPerLane; ++q) {
+    const int c = grp + kGroups * q;
+    w[q] = (c < bbc && g < kc) ? W[(pj + c) * ldw + g] : (ST)0;
+  }
+  TileRegs<ST> tr;
+  if (j > 0) tile_issue_a(tr, L, ldl, 0, pj, bbc);
+#pragma unroll
+  for (int q = 0; q < kTilePerThread; ++q) {
+    const int idx = tid + q * kThreads;
+    sh.Lb[idx >> 6][idx & 63] = (double)lt[q];
+  }
+  // identity records everywhere: the pad rows keep them, each block's rows
+  // are overwritten as they arrive
+  for (int idx = tid; idx < kRRows * kKP; idx += kThreads) sh.R[idx >> 4][idx & 15] = identity_rec();
+  for (int b = 0; b < j; ++b) {
+    __syncthreads();  // sh.A is free again
+    tile_stage(sh, tr);
+    if (b + 1 < j) tile_issue_a(tr, L, ldl, (int64_t)(b + 1) * kBR, pj, bbc);
+    owner_apply<SG, ST, KCF>(sh, L, ldl, kc, (int64_t)b * kBR, pj, bbc, w, T, deadline);
+  }
+  __syncthreads();
+  // V of the block's columns, after all earlier rows, starts the chain
+#pragma unroll
+  for (int q = 0; q < kColsPerLane; ++q) {
+    const int c = grp + kGroups * q;
+    if (g < kc) sh.Hb[g][1][c] = c < bbc ? (double)w[q] : 0.0;
+  }
+  chain_setup(sh, bbc);
+  __syncthreads();
+  chain_loops<SG, ST, KCF>(sh, kc, bbc, pj + kBR < n, T, pj);
+  chain_finish(sh, L, ldl, kc, kfull, m0, pj, bbc, info, stop_row);
+  if (tid == 0 && sh.tmo)
+    atomicMin((unsigned long long*)info,
+              (unsigned long long)info_key(pj * kfull + m0, kCodeTimeout));
+}
+
+// Records of one pass start out empty.
+template <typename ST>
+__global__ void k_owner_clear(GRec<ST>* __restrict__ T, int64_t words) {
+  using U = typename RecBits<ST>::U;
+  U* __restrict__ p = reinterpret_cast<U*>(T);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+    p[i] = RecBits<ST>::kEmpty;
 }
 
 // Batched form: the launch of step s holds, for every factor with more than
@@ -805,21 +925,21 @@ __global__ __launch_bounds__(kThreads) void k_sb_batch(const BatchFactor* __rest
     double* W = (double*)F.W + E.m0;
     GRec<double>* T = (GRec<double>*)F.T;
     if (F.sigma > 0)
-      block_work<1, double, 0, false>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
-                            F.info, F.stop, wg, 0, 0, nullptr);
+      block_work<1, double, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+                               F.info, F.stop, wg);
     else
-      block_work<-1, double, 0, false>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
-                             F.info, F.stop, wg, 0, 0, nullptr);
+      block_work<-1, double, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+                                F.info, F.stop, wg);
   } else {
     float* L = (float*)F.L;
     float* W = (float*)F.W + E.m0;
     GRec<float>* T = (GRec<float>*)F.T;
     if (F.sigma > 0)
-      block_work<1, float, 0, false>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
-                           F.info, F.stop, wg, 0, 0, nullptr);
+      block_work<1, float, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+                              F.info, F.stop, wg);
     else
-      block_work<-1, float, 0, false>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
-                            F.info, F.stop, wg, 0, 0, nullptr);
+      block_work<-1, float, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+                               F.info, F.stop, wg);
   }
 }
 
@@ -839,29 +959,24 @@ __global__ void k_prepare_batch(const BatchFactor* __restrict__ fac) {
     dst[i] = src[i];
 }
 
+// One owner launch per pass; tickets[p] (zero before the first pass) counts
+// the workgroups of pass p as they start.
 template <typename ST>
 hipError_t run_sysblk_t(hipStream_t st, ST* L, int64_t n, int64_t ldl, ST* W, int64_t k, int sg,
-                        void* Tws, int64_t* info, int64_t* stop, int32_t* flags) {
+                        void* Tws, int64_t* info, int64_t* stop, int32_t* tickets) {
   GRec<ST>* R = reinterpret_cast<GRec<ST>*>(Tws);
   const int64_t nb = (n + kBR - 1) / kBR;
+  const int64_t words = n * kKP * 4;
+  const int64_t cblocks = (words + 255) / 256;
+  const unsigned cgrid = (unsigned)(cblocks < 1024 ? cblocks : 1024);
   for (int64_t m0 = 0; m0 < k; m0 += kKP) {
     const int kc = (int)((k - m0) < kKP ? (k - m0) : kKP);
-    ST* Wc = W + m0;
-    for (int64_t pc = 0; pc < n; pc += kBR) {
-      const int bbc = (int)((n - pc) < kBR ? (n - pc) : kBR);
-      const int64_t pa = pc - kBR;  // previous block (always full), or < 0
-      const int bbc1 = (int)((n - pc - bbc) < kBR ? (n - pc - bbc) : kBR);  // next block's rows
-      const int H = (bbc1 + kHeadCols - 1) / kHeadCols;
-      const int64_t rest = n - (pc + bbc + bbc1);
-      const unsigned grid =
-          1u + (unsigned)H + (pa >= 0 ? (unsigned)((rest + kBR - 1) / kBR) : 0u);
-      int32_t* flag = flags + (m0 / kKP) * nb + pc / kBR;
-      // full passes (16 columns of V) use a variant specialised on that width
-      auto kern = sg > 0 ? (kc == kKP ? k_sb_block<1, ST, kKP> : k_sb_block<1, ST, 0>)
-                         : (kc == kKP ? k_sb_block<-1, ST, kKP> : k_sb_block<-1, ST, 0>);
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, L, ldl, Wc, k, kc, k, m0, n, pc,
-                         bbc, pa, R, info, stop, H, bbc1, flag);
-    }
+    hipLaunchKernelGGL(k_owner_clear<ST>, dim3(cgrid), dim3(256), 0, st, R, words);
+    // full passes (16 columns of V) use a variant specialised on that width
+    auto kern = sg > 0 ? (kc == kKP ? k_sb_owner<1, ST, kKP> : k_sb_owner<1, ST, 0>)
+                       : (kc == kKP ? k_sb_owner<-1, ST, kKP> : k_sb_owner<-1, ST, 0>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreads), 0, st, L, ldl,
+                       (const ST*)(W + m0), k, kc, k, m0, n, R, info, stop, tickets + m0 / kKP);
   }
   return hipGetLastError();
 }
@@ -884,19 +999,20 @@ hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t co
   return hipGetLastError();
 }
 
-// Fast blocked schedule: V columns in passes of 16, one launch per block of
-// 64 rows.  W is the private copy of V (row stride k); T holds n x 16 records.
+// Fast blocked schedule: V columns in passes of 16, one owner launch per
+// pass.  W is the private copy of V (row stride k); T holds n x 16 records;
+// tickets holds one zeroed int32 per pass.
 hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
-                      double sg, Coef* T, int64_t* info, int64_t* stop, int32_t* flags) {
-  return run_sysblk_t<double>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, flags);
+                      double sg, Coef* T, int64_t* info, int64_t* stop, int32_t* tickets) {
+  return run_sysblk_t<double>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets);
 }
 
 // The same schedule with L, V and the records stored in FP32: the rows of a
 // block (Compute and the Apply inside the block) run in FP64 from the FP32
 // values, the Apply to other blocks' columns runs in FP32.
 hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, float* W, int64_t k,
-                          double sg, void* T, int64_t* info, int64_t* stop, int32_t* flags) {
-  return run_sysblk_t<float>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, flags);
+                          double sg, void* T, int64_t* info, int64_t* stop, int32_t* tickets) {
+  return run_sysblk_t<float>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets);
 }
 
 }  // namespace chm
