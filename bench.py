@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
-PROFILE = os.path.join(ROOT, "profiles", "k_sb_block_n5000_k16.md")
+PROFILE = os.path.join(ROOT, "profiles", "k_sb_owner_n5000_k16.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1011_1173_amd", "csrc", "sysblk.hip")
 
 
@@ -275,17 +275,16 @@ def main():
     mean = sum(per) / len(per)
     alg_bytes = 8.0 * n * (n + 1) + 8.0 * n * k
     ms_per_step = total_ms / K
-    # Dominant kernel: the per-block launch of the fast schedule.  One
-    # modification is one launch per 64-row block and 16-column pass of V
-    # (plus one small preparation launch), back to back on `stream`; the
-    # events above bracket all of them, so the average launch duration is
-    # taken as the modification time over the block launches (inter-launch
-    # gaps and the preparation launch included: a conservative figure).
-    blocks = (n + 63) // 64
+    # Dominant kernel: the owner launch of the fast schedule, one per
+    # 16-column pass of V.  A modification is a preparation launch (W <- V),
+    # then per pass a clear launch (empty records) and the owner launch, back
+    # to back on `stream`; the events above bracket all of them, so the
+    # owner launch's duration is taken as the modification time over the
+    # passes (the two small launches included: a conservative figure).
     passes = (k + 15) // 16
-    launches = blocks * passes
+    launches = passes
     avg_launch_us = mean * 1e3 / launches
-    bytes_per_launch = alg_bytes / (blocks * passes)
+    bytes_per_launch = alg_bytes / passes
     achieved = bytes_per_launch / (avg_launch_us * 1e-6) / 1e9
     out = {
         "metric": "updates/s + effective HBM GB/s (n=5000,k=16); served p50/p99 latency",
@@ -303,8 +302,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if (n, k) == (5000, 16) else None,
-                     "kernel": "k_sb_block (one launch per 64-row block)",
-                     "launches_per_modification": launches + 1,
+                     "kernel": "k_sb_owner (one launch per 16-column pass)",
+                     "launches_per_modification": 1 + 2 * passes,
                      "avg_launch_us": avg_launch_us,
                      "alg_bytes_per_launch": bytes_per_launch},
         "round_trip_drift": drift,

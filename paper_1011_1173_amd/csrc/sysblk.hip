@@ -107,6 +107,7 @@ struct SbLds {
   int fail;                 // first failing (row * 16 + column) of the block
   int tk;                   // owner schedule: this workgroup's ticket
   int tmo;                  // owner schedule: a wait ran out of time
+  int up[2];                // owner schedule: rows of the applied block staged, by round parity
 };
 
 __device__ __forceinline__ double sb_shr1(double x, double fill) {
@@ -475,14 +476,11 @@ __device__ __forceinline__ void helper_steps(SbLds& sh, int nsteps, int lane, in
   }
 }
 
-// LDS set-up of a chain (the block's triangle staged in sh.Lb): identity
-// records for the block's rows until wave 0 writes them, the helpers'
-// transfer rows cleared, and each row's diagonal and lane 0's inputs.
-__device__ __forceinline__ void chain_setup(SbLds& sh, int bbc) {
+// LDS set-up of a chain that needs only the block's triangle (staged in
+// sh.Lb): the helpers' transfer rows cleared, and each row's diagonal and
+// lane 0's inputs.
+__device__ __forceinline__ void chain_setup_tri(SbLds& sh, int bbc) {
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < kRRows * kKP; idx += kThreads) {
-    if ((idx >> 4) >= kPad) sh.R[idx >> 4][idx & 15] = identity_rec();
-  }
   for (int idx = tid; idx < 5 * kBR; idx += kThreads) sh.X[idx >> 6][1][idx & 63] = 0.0;
   if (tid == 0) sh.fail = 0x7fffffff;
   if (tid < kRRows) {
@@ -502,21 +500,32 @@ __device__ __forceinline__ void chain_setup(SbLds& sh, int bbc) {
   }
 }
 
-// Wave 4 (owner schedule): the records of rows [r0, r0 + 16) of block
+// Identity records for the block's rows until wave 0 writes them.  (A full
+// block could do without: every row a helper reads has been written by wave
+// 0 one step earlier.)
+__device__ __forceinline__ void chain_setup_records(SbLds& sh) {
+  for (int idx = threadIdx.x; idx < kRRows * kKP; idx += kThreads) {
+    if ((idx >> 4) >= kPad) sh.R[idx >> 4][idx & 15] = identity_rec();
+  }
+}
+
+__device__ __forceinline__ void chain_setup(SbLds& sh, int bbc) {
+  chain_setup_records(sh);
+  chain_setup_tri(sh, bbc);
+}
+
+// Wave 4 (owner schedule): the records of rows [r0, r0 + 4) of block
 // [pc, pc + 64), complete in sh.R, go to T for the owners of later blocks.
 template <typename ST>
 __device__ __forceinline__ void publish_rows(SbLds& sh, GRec<ST>* __restrict__ T, int64_t pc,
                                              int r0, int kc, int lane) {
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int e = lane + 64 * v, r = r0 + (e >> 4), m = e & 15;
-    if (m < kc) publish_record(T + (pc + r) * kKP + m, sh.R[r + kPad][m]);
-  }
+  const int r = r0 + (lane >> 4), m = lane & 15;
+  if (m < kc) publish_record(T + (pc + r) * kKP + m, sh.R[r + kPad][m]);
 }
 
 // The step loops of the chain of block [pc, pc + bbc); sh is set up and V of
 // the block's columns is in sh.Hb parity 1.  pub (full blocks with a later
-// block only): wave 4 publishes the records 16 rows at a time as they
+// block only): wave 4 publishes the records 4 rows at a time as they
 // complete.  After barrier u of the loop (u = 0 .. nsteps) the rows up to
 // u - kc are complete: row i's last record is written at step i + kc - 1.
 template <int SG, typename ST, int KCF>
@@ -539,8 +548,8 @@ __device__ __forceinline__ void chain_loops(SbLds& sh, int kc, int bbc, bool pub
     int q = 0;
     for (int u = 0; u <= nsteps; ++u) {
       __syncthreads();
-      if (pub && q < kBR / 16 && u == 16 * q + 15 + kc) {
-        publish_rows(sh, T, pc, 16 * q, kc, lane);
+      if (pub && q < kBR / 4 && u == 4 * q + 3 + kc) {
+        publish_rows(sh, T, pc, 4 * q, kc, lane);
         ++q;
       }
     }
@@ -718,109 +727,149 @@ __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_
 // started (then the launch reports kCodeTimeout and its results are void).
 constexpr int64_t kWaitTicks = 500000000;  // steady-counter ticks (5 s at 100 MHz)
 
-// Apply block [pb, pb + 64) to the owner's columns [j0, j0 + ncols) (tile
-// staged in sh.A; w: this thread's V values, lane g of group grp: columns
-// grp + 32 q, column g of V).  The records arrive 16 rows at a time; the
-// sub-steps that need rows of the next 16 wait for them.  Same operations,
-// in the same order, as apply_tile.
+// The owner's apply runs on waves 0-3, one per SIMD: lane g of 16-lane group
+// grp (0..15) applies rotation g of row s - g at sub-step s to the four
+// columns grp + 16 u, so each record read from LDS serves four columns.
+// Wave 4 fetches the records: it waits until a prefix of the next 16 rows
+// has been published, stages those rows in sh.R and announces how far the
+// staged rows go (sh.up, by round parity); the apply waves then run the
+// sub-steps whose rows are all staged, while wave 4 fetches the next rows.
+// Waves 5-7 only pass the rounds' barriers.
+constexpr int kOwnCols = 4;
+constexpr int kOwnGroups = 16;
+constexpr int kOwnThreads = kOwnGroups * 16;  // 256
+
+// Apply block [pb, pb + 64) (tile staged in sh.A, the caller has
+// synchronised) to the owner's columns; w: an apply lane's V values.  next:
+// block pb is the one just before the owner's own (its chain waits for this
+// apply), so wave 4 polls without delay; the owners further right poll
+// slowly, which keeps their reads of the same few records from crowding the
+// memory channels.  Same operations, in the same order, as apply_tile.
 template <int SG, typename ST, int KCF>
-__device__ __forceinline__ void owner_apply(SbLds& sh, ST* __restrict__ L, int64_t ldl, int kc_,
-                                            int64_t pb, int64_t j0, int ncols,
-                                            ST (&w)[kColsPerLane],
-                                            const GRec<ST>* __restrict__ T, int64_t deadline) {
+__device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
+                                            ST (&w)[kOwnCols],
+                                            const GRec<ST>* __restrict__ T, int64_t deadline,
+                                            bool next) {
   using U = typename RecBits<ST>::U;
   constexpr U kE = RecBits<ST>::kEmpty;
-  constexpr int NQ = kColsPerLane;
   const int kc = KCF ? KCF : kc_;
   const int tid = threadIdx.x;
-  const int g = tid & 15, grp = tid >> 4;
-  // this thread's records: (row, column) = ((tid + 512 e) >> 4, tid & 15),
-  // e = 0, 1, so rows [16 q, 16 q + 16) are held by e = q / 2 of the threads
-  // with tid / 256 = q % 2
-  const int mr = tid & 15;
-  U rb[2][3];
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int r = (tid + kThreads * e) >> 4;
-    if (mr < kc) {
-      const GRec<ST>* src = T + (pb + r) * kKP + mr;
-      rb[e][0] = load_bits(&src->c);
-      rb[e][1] = load_bits(&src->s);
-      rb[e][2] = load_bits(&src->ic);
-    }
-  }
-  ST xin[NQ], nxt[NQ];
-  const RotRec* rp = &sh.R[kPad - g][g];  // record of row s - g at rp[s * kKP]
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int S = kBR + kc - 1;
+  if (wv < 4) {
+    const int g = lane & 15, grp = tid >> 4;
+    ST xin[kOwnCols], nxt[kOwnCols];
 #pragma unroll
-  for (int q = 0; q < kBR / 16; ++q) {
-    const int e = q >> 1;
-    if ((tid >> 8) == (q & 1) && mr < kc) {
-      const int r = (tid + kThreads * e) >> 4;
-      U c = rb[e][0], s = rb[e][1], ic = rb[e][2];
-      if (c == kE || s == kE || ic == kE) {
-        const GRec<ST>* src = T + (pb + r) * kKP + mr;
-        do {
-          __builtin_amdgcn_s_sleep(1);
-          c = load_bits(&src->c);
-          s = load_bits(&src->s);
-          ic = load_bits(&src->ic);
-          if (wall_clock64() > deadline) {
-            sh.tmo = 1;
-            break;
-          }
-        } while (c == kE || s == kE || ic == kE);
-      }
-      RotRec rec;
-      rec.c = (double)__builtin_bit_cast(ST, c);
-      rec.s = (double)__builtin_bit_cast(ST, s);
-      rec.ic = (double)__builtin_bit_cast(ST, ic);
-      rec.ss = 0.0;
-      sh.R[kPad + r][mr] = rec;
+    for (int u = 0; u < kOwnCols; ++u) {
+      xin[u] = (ST)sh.A[0][grp + kOwnGroups * u];
+      nxt[u] = (ST)sh.A[1][grp + kOwnGroups * u];
     }
-    __syncthreads();
-    if (q == 0) {
+    const RotRec* rp = &sh.R[kPad - g][g];  // record of row s - g at rp[s * kKP]
+    int s = 0;
+    for (int rd = 0;; ++rd) {
+      __syncthreads();
+      const int up = sh.up[rd & 1];
+      const int lim = up >= kBR ? S : up;  // rows <= s - g < up are staged
+      RotRec cf = rp[s * kKP];
+      for (; s < lim; ++s) {
+        const int r = s - g;
+        const RotRec cfn = rp[imin(s + 1, kBR + kKP - 1 + g) * kKP];  // row <= 79
+        ST nxt2[kOwnCols];
+        if (g == 0) {
+          const int rn2 = imin(s + 2, kBR - 1);
 #pragma unroll
-      for (int u = 0; u < NQ; ++u) {
-        xin[u] = (ST)sh.A[0][grp + kGroups * u];
-        nxt[u] = (ST)sh.A[1][grp + kGroups * u];
+          for (int u = 0; u < kOwnCols; ++u) nxt2[u] = (ST)sh.A[rn2][grp + kOwnGroups * u];
+        }
+        const ST c = (ST)cf.c, sn = (ST)cf.s, ic = (ST)cf.ic;
+        ST x[kOwnCols];
+#pragma unroll
+        for (int u = 0; u < kOwnCols; ++u) {
+          x[u] = fma_t((ST)SG * sn, w[u], xin[u]) * ic;
+          w[u] = fma_t(-sn, x[u], c * w[u]);
+        }
+        if (g == kc - 1 && r >= 0 && r < kBR) {
+#pragma unroll
+          for (int u = 0; u < kOwnCols; ++u) sh.A[r][grp + kOwnGroups * u] = x[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kOwnCols; ++u) {
+          xin[u] = sb_shr1(x[u], nxt[u]);
+          nxt[u] = nxt2[u];
+        }
+        cf = cfn;
       }
+      if (up >= kBR) break;
     }
-    const int s_end = q == kBR / 16 - 1 ? S : 16 * q + 16;
-    RotRec cf = rp[16 * q * kKP];
-    for (int s = 16 * q; s < s_end; ++s) {
-      const int r = s - g;
-      const RotRec cfn = rp[imin(s + 1, kBR + kKP - 1 + g) * kKP];  // row <= 79
-      ST nxt2[NQ];
-      if (g == 0) {
-        const int rn2 = imin(s + 2, kBR - 1);
+  } else if (wv == 4) {
+    // lane holds rows up + 4 v + lane / 16 (v = 0..3) of the window, column m
+    const int m = lane & 15, rl = lane >> 4;
+    U f[4][3];
+    auto fetch = [&](int up) {
 #pragma unroll
-        for (int u = 0; u < NQ; ++u) nxt2[u] = (ST)sh.A[rn2][grp + kGroups * u];
+      for (int v = 0; v < 4; ++v) {
+        const int r = up + 4 * v + rl;
+        if (r < kBR && m < kc) {
+          const GRec<ST>* src = T + (pb + r) * kKP + m;
+          f[v][0] = load_bits(&src->c);
+          f[v][1] = load_bits(&src->s);
+          f[v][2] = load_bits(&src->ic);
+        } else {
+          f[v][0] = f[v][1] = f[v][2] = 0;  // nothing to wait for
+        }
       }
-      const ST c = (ST)cf.c, sn = (ST)cf.s, ic = (ST)cf.ic;
-      ST x[NQ];
+    };
+    // rows of the window (bit 4 v + group) whose records are all there
+    auto ready_rows = [&]() {
+      uint32_t full = 0;
 #pragma unroll
-      for (int u = 0; u < NQ; ++u) {
-        x[u] = fma_t((ST)SG * sn, w[u], xin[u]) * ic;
-        w[u] = fma_t(-sn, x[u], c * w[u]);
-      }
-      if (g == kc - 1 && r >= 0 && r < kBR) {
+      for (int v = 0; v < 4; ++v) {
+        const bool ok = f[v][0] != kE && f[v][1] != kE && f[v][2] != kE;
+        const uint64_t b = __ballot(ok);
 #pragma unroll
-        for (int u = 0; u < NQ; ++u) sh.A[r][grp + kGroups * u] = x[u];
+        for (int gq = 0; gq < 4; ++gq)
+          if (((b >> (16 * gq)) & 0xFFFFull) == 0xFFFFull) full |= 1u << (4 * v + gq);
       }
+      return full;
+    };
+    int up = 0;
+    fetch(0);
+    for (int rd = 0;; ++rd) {
+      int nr = __builtin_ctz(~ready_rows());
+      while (nr == 0) {
+        if (wall_clock64() > deadline) {  // give up: stage what is there
+          sh.tmo = 1;
+          nr = 16;
+          break;
+        }
+        if (next) __builtin_amdgcn_s_sleep(1);
+        else __builtin_amdgcn_s_sleep(100);
+        fetch(up);
+        nr = __builtin_ctz(~ready_rows());
+      }
+      if (nr > kBR - up) nr = kBR - up;
 #pragma unroll
-      for (int u = 0; u < NQ; ++u) {
-        xin[u] = sb_shr1(x[u], nxt[u]);
-        nxt[u] = nxt2[u];
+      for (int v = 0; v < 4; ++v) {
+        const int r = up + 4 * v + rl;
+        if (4 * v + rl < nr && m < kc) {
+          RotRec rec;
+          rec.c = (double)__builtin_bit_cast(ST, f[v][0]);
+          rec.s = (double)__builtin_bit_cast(ST, f[v][1]);
+          rec.ic = (double)__builtin_bit_cast(ST, f[v][2]);
+          rec.ss = 0.0;
+          sh.R[kPad + r][m] = rec;
+        }
       }
-      cf = cfn;
+      up += nr;
+      if (lane == 0) sh.up[rd & 1] = up;
+      if (up < kBR) fetch(up);  // in flight while the apply waves run
+      __syncthreads();
+      if (up >= kBR) break;
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kTilePerThread; ++q) {
-    const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
-    if (c < ncols) L[(pb + r) * ldl + j0 + c] = (ST)sh.A[r][c];
+  } else {
+    for (int rd = 0;; ++rd) {
+      __syncthreads();
+      if (sh.up[rd & 1] >= kBR) break;
+    }
   }
 }
 
@@ -850,11 +899,11 @@ __global__ __launch_bounds__(kThreads) void k_sb_owner(
     lt[q] = (i < bbc && c < bbc && c >= i) ? L[(pj + i) * ldl + pj + c] : (ST)0;
   }
   const int g = tid & 15, grp = tid >> 4;
-  ST w[kColsPerLane];
+  ST w[kOwnCols];
 #pragma unroll
-  for (int q = 0; q < kColsPerLane; ++q) {
-    const int c = grp + kGroups * q;
-    w[q] = (c < bbc && g < kc) ? W[(pj + c) * ldw + g] : (ST)0;
+  for (int u = 0; u < kOwnCols; ++u) {
+    const int c = grp + kOwnGroups * u;
+    w[u] = (tid < kOwnThreads && c < bbc && g < kc) ? W[(pj + c) * ldw + g] : (ST)0;
   }
   TileRegs<ST> tr;
   if (j > 0) tile_issue_a(tr, L, ldl, 0, pj, bbc);
@@ -866,20 +915,31 @@ __global__ __launch_bounds__(kThreads) void k_sb_owner(
   // identity records everywhere: the pad rows keep them, each block's rows
   // are overwritten as they arrive
   for (int idx = tid; idx < kRRows * kKP; idx += kThreads) sh.R[idx >> 4][idx & 15] = identity_rec();
+  __syncthreads();
+  chain_setup_tri(sh, bbc);  // needs only the triangle: done before the applies
   for (int b = 0; b < j; ++b) {
     __syncthreads();  // sh.A is free again
     tile_stage(sh, tr);
     if (b + 1 < j) tile_issue_a(tr, L, ldl, (int64_t)(b + 1) * kBR, pj, bbc);
-    owner_apply<SG, ST, KCF>(sh, L, ldl, kc, (int64_t)b * kBR, pj, bbc, w, T, deadline);
-  }
-  __syncthreads();
-  // V of the block's columns, after all earlier rows, starts the chain
+    const int64_t pb = (int64_t)b * kBR;
+    __syncthreads();
+    owner_apply<SG, ST, KCF>(sh, kc, pb, w, T, deadline, b == j - 1);
+    __syncthreads();
 #pragma unroll
-  for (int q = 0; q < kColsPerLane; ++q) {
-    const int c = grp + kGroups * q;
-    if (g < kc) sh.Hb[g][1][c] = c < bbc ? (double)w[q] : 0.0;
+    for (int q = 0; q < kTilePerThread; ++q) {
+      const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
+      if (c < bbc) L[(pb + r) * ldl + pj + c] = (ST)sh.A[r][c];
+    }
   }
-  chain_setup(sh, bbc);
+  // V of the block's columns, after all earlier rows, starts the chain
+  if (tid < kOwnThreads && g < kc) {
+#pragma unroll
+    for (int u = 0; u < kOwnCols; ++u) {
+      const int c = grp + kOwnGroups * u;
+      sh.Hb[g][1][c] = c < bbc ? (double)w[u] : 0.0;
+    }
+  }
+  if (bbc < kBR) chain_setup_records(sh);
   __syncthreads();
   chain_loops<SG, ST, KCF>(sh, kc, bbc, pj + kBR < n, T, pj);
   chain_finish(sh, L, ldl, kc, kfull, m0, pj, bbc, info, stop_row);
