@@ -53,9 +53,12 @@ def parse():
     ap.add_argument("--n", type=int, default=5000)
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--mode", choices=["headline", "served"], default="headline",
-                    help="headline: one factor, n=5000, k=16 (default); served: a pool of "
-                         "factors fed by Poisson arrivals through the served mode")
+    ap.add_argument("--mode", choices=["headline", "batched", "served"], default="headline",
+                    help="headline: one factor, n=5000, k=16 (default); batched: 256 factors "
+                         "of uneven size per call; served: a pool of factors fed by Poisson "
+                         "arrivals through the served mode")
+    ap.add_argument("--batch-dtype", choices=["f64", "f32s"], default="f64",
+                    help="batched mode: storage type of the factors")
     ap.add_argument("--served-seconds", type=float, default=3.0,
                     help="served mode: arrival window per load level")
     ap.add_argument("--served-factors", type=int, default=64)
@@ -89,6 +92,86 @@ def cpu_baseline(L, V, budget_s=10.0):
                       "%.1f s on one host core" % (mods, V.shape[1], L.shape[0], dt)}
 
 
+def batched(args):
+    """Batched workload: 256 factors with n ~ U{64..4096} and k ~ U{1..32}
+    (seeded), each with 2 V's already added (untimed).  One timed batch gives
+    every factor either an update by a new V or the downdate of a V still in
+    its added set (50/50), through one cholmod_update_batched call.  Reports
+    modifications/s and the algorithmic bytes of the batch over its time."""
+    import random
+    import torch
+    import paper_1011_1173_amd as chm
+    from paper_1011_1173_amd import inputs
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    dt = torch.float64 if args.batch_dtype == "f64" else torch.float32
+    es = 8 if dt == torch.float64 else 4
+    rng = random.Random(4)
+    nf = 256
+    ns = [rng.randint(64, 4096) for _ in range(nf)]
+    Ls = [inputs.spd_factor(n, seed=4000 + f, device="cuda").to(dt) for f, n in enumerate(ns)]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4242)
+
+    def new_v(n):
+        k = rng.randint(1, 32)
+        return (torch.randn(n, k, generator=gen, device="cuda", dtype=torch.float64)
+                / math.sqrt(n)).to(dt)
+
+    added = [[] for _ in range(nf)]
+    for _ in range(2):  # prior V's, untimed
+        Vs = [new_v(n) for n in ns]
+        st = chm.update_batched(Ls, Vs, [1] * nf)
+        assert all(x[0] == 0 for x in st), st
+        for f in range(nf):
+            added[f].append(Vs[f])
+    torch.cuda.synchronize()
+
+    def make_batch():
+        Vs, sg = [], []
+        for f in range(nf):
+            if rng.random() < 0.5 or not added[f]:
+                V = new_v(ns[f])
+                added[f].append(V)
+                Vs.append(V)
+                sg.append(1)
+            else:
+                Vs.append(added[f].pop(rng.randrange(len(added[f]))))
+                sg.append(-1)
+        return Vs, sg
+
+    stream = torch.cuda.Stream()
+    batches = [make_batch() for _ in range(args.warmup + args.steps)]
+    ws = None
+    times, byts = [], []
+    for i, (Vs, sg) in enumerate(batches):
+        with torch.cuda.stream(stream):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            pb = chm.update_batched_async(Ls, Vs, sg, stream=stream)
+            e1.record(stream)
+        st = pb.statuses()
+        assert all(x[0] == 0 for x in st), st
+        if i >= args.warmup:
+            times.append(e0.elapsed_time(e1))
+            byts.append(sum(es * n * (n + 1) + es * n * V.shape[1] for n, V in zip(ns, Vs)))
+    ts = sorted(times)
+    med = ts[len(ts) // 2]
+    out = {"metric": "batched modifications/s (256 uneven factors per call)",
+           "value": nf / (med * 1e-3), "unit": "modifications/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": med,
+           "higher_is_better": True, "dtype": args.batch_dtype, "data": "synthetic",
+           "config": {"workload": "batched: 256 factors, n ~ U{64..4096}, k ~ U{1..32}, "
+                                  "update or downdate 50/50 per factor",
+                      "dense_GB": sum(es * n * n for n in ns) / 1e9},
+           "batch_ms": {"median": med, "min": ts[0], "max": ts[-1]},
+           "effective_GBps": (sum(byts) / len(byts)) / (med * 1e-3) / 1e9}
+    print(json.dumps(out))
+    return 0
+
+
 def served(args):
     """Served workload: a pool of factors with sizes cycled over {1024, 2048,
     4096, 8192, 16384}, each with 4 prior V's already added (untimed).  A
@@ -111,6 +194,9 @@ def served(args):
         n = sizes[f % len(sizes)]
         factors.append(inputs.spd_factor(n, seed=5 + f, device="cuda"))
         windows.append([])
+        if f % 8 == 7:
+            torch.cuda.synchronize()
+            print("served: %d factors built" % (f + 1), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     gen = torch.Generator(device="cuda")
     gen.manual_seed(12345)
@@ -125,6 +211,7 @@ def served(args):
             chm.update(L, V, +1)
             windows[f].append(V)
     torch.cuda.synchronize()
+    print("served: prior V's added", file=sys.stderr, flush=True)
     dense_gb = sum(8.0 * L.shape[0] * L.shape[1] for L in factors) / 1e9
     srv = chm.Server(ws_bytes=6 << 30, max_batch=nf)
     ids = [srv.add_factor(L) for L in factors]
@@ -172,6 +259,7 @@ def served(args):
     sat_s = time.perf_counter() - t0
     wait_all(pairs)
     sat_rate = burst / sat_s  # request pairs per second
+    print("served: saturated %.1f pairs/s" % sat_rate, file=sys.stderr, flush=True)
     levels = []
     for frac in (0.25, 0.50, 0.75, 0.90):
         rate = frac * sat_rate
@@ -194,6 +282,7 @@ def served(args):
         span = time.perf_counter() - t_start
         lat = sorted(wait_all(pairs))
         cnt = len(lat)
+        print("served: load %.2f done, %d pairs" % (frac, cnt), file=sys.stderr, flush=True)
         levels.append({"load": frac, "offered_pairs_per_s": rate, "pairs": cnt,
                        "updates_per_s": 2.0 * cnt / span,
                        "p50_ms": 1e3 * lat[cnt // 2] if cnt else None,
@@ -218,6 +307,8 @@ def main():
               "nothing here uses more than one device (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
         return 2
+    if args.mode == "batched":
+        return batched(args)
     if args.mode == "served":
         return served(args)
     import torch
