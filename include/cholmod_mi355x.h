@@ -44,7 +44,11 @@
  *   default (fast): the same rotations, evaluated with reciprocal square
  *     roots refined by Newton steps, multiplication by 1/c instead of
  *     division, and fused multiply-adds; results agree with the exact
- *     evaluation to a relative residual far below 1e-12.
+ *     evaluation to a relative residual far below 1e-12.  The fast mode's
+ *     single launch per 16 columns of V has workgroups wait for records
+ *     that earlier workgroups publish; such a wait is bounded, and a launch
+ *     whose wait ran out (not expected while the GPU runs the launch)
+ *     reports CHOLMOD_ERR_HIP.
  */
 #ifndef CHOLMOD_MI355X_H
 #define CHOLMOD_MI355X_H
@@ -136,8 +140,8 @@ int cholmod_update_ex(double *L, const double *V, int64_t n, int64_t k, int64_t 
  * stored in binary32.  The rows of each 64-row diagonal block -- every
  * Compute (w, c, s, 1/c) and the Apply inside the block -- are evaluated in
  * binary64 from the stored values and rounded to binary32 when stored; the
- * Apply of a block's rotations to the columns right of the next block runs
- * in binary32 with the coefficients rounded to binary32.  Accuracy: the
+ * Apply of a block's rotations to the columns right of the block runs in
+ * binary32 with the coefficients rounded to binary32.  Accuracy: the
  * relative Frobenius distance to the binary64 factor of the same (binary32)
  * inputs is about 1e-6 (bound tested: 1e-5).  Halves the memory traffic;
  * the serial chain is unchanged.  Layout, ownership and error reporting are

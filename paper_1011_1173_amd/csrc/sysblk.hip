@@ -1,16 +1,26 @@
-// sysblk.hip -- blocked schedule of CholeskyModifyB for the fast evaluation
-// mode.  Rows are processed in blocks of 64 and the columns of V in passes
-// of up to 16.  One kernel launch per block b does all the work that becomes
-// possible once block b-1 is finished:
+// sysblk.hip -- blocked schedules of CholeskyModifyB for the fast
+// evaluation mode.  Rows are processed in blocks of 64 and the columns of V
+// in passes of up to 16.  The work of a block splits into its chain (the
+// rows of the block: Compute, and the Apply inside its 64 x 64 triangle)
+// and the Apply of its rows to the columns right of it.
 //
-//   workgroup 0 ("chain"):  applies the rotations of block b-1 to the 64
-//     columns of block b (the head tile), then runs the rows of block b from
-//     LDS and writes the block's rotation records for the next launch;
-//   workgroups 1.. ("rest"): apply the rotations of block b-1 to the columns
-//     to the right of block b, 64 columns each, concurrently with the chain.
+// Single factor: one persistent launch per pass (the owner schedule,
+// k_sb_owner).  Workgroup j, by the order in which workgroups start, owns
+// the columns of block j: it applies blocks 0 .. j-1 to them in row order,
+// each as the owner of that block publishes its records, then runs the
+// chain of block j and publishes that block's records 4 rows at a time
+// while the chain runs.  V of the owner's columns never leaves the
+// workgroup, and the owner of block j+1 applies block j while its chain is
+// still running, so the chains follow each other with only the last rows'
+// Apply between them.
+//
+// Batches: one launch per block step (k_sb_batch).  Workgroup 0 of a
+// factor's step applies block b-1 to the columns of block b, then runs the
+// chain of block b and writes its records for the next launch; the other
+// workgroups apply block b-1 to the columns right of block b.
 //
 // Every element goes through the same fast-mode operations (rotations.h) in
-// the same order as in the per-row schedule, so both schedules give results
+// the same order as in the per-row schedule, so all schedules give results
 // that are identical bit for bit.
 //
 // The chain.  Algorithm 1 is serial through the rows: Compute(i, m) needs
@@ -36,17 +46,18 @@
 // step loop touches no global memory; a failing Compute is remembered per
 // lane and reported after the loop.
 //
-// The apply tiles (head and rest).  A tile is 64 rows (the block) by 64
-// columns.  Lane g of a 16-lane group applies rotation g of row s - g at
-// sub-step s to two columns, so each record read from LDS serves two
-// columns; the partly rotated L_rj moves to lane g+1 with a DPP row shift
-// and each lane keeps its two V_j[g] in registers.  Two waves per SIMD hide
-// each other's latencies.
+// The apply tiles.  A tile is 64 rows (a block) by 64 columns.  Lane g of a
+// 16-lane group applies rotation g of row s - g at sub-step s to several
+// columns (two in the batch form, four in the owner's), so each record read
+// from LDS serves all of them; the partly rotated L_rj moves to lane g+1
+// with a DPP row shift and each lane keeps its V_j[g] in registers.
 //
 // Failures.  After a failure at row r the contents of rows >= r are
 // unspecified, so nothing inside a block depends on a failure: the first
-// failure is recorded with atomic minima (index/code, row), and launches
-// for later blocks and passes skip the rows at or after it.
+// failure is recorded with atomic minima (index/code, row).  The batch
+// form's launches for later blocks and passes skip the rows at or after
+// it; the owner schedule simply carries on (every later value is
+// unspecified) and the first failure stays the reported one.
 #include "rotations.h"
 #include "batch.h"
 
