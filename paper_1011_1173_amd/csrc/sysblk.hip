@@ -121,19 +121,27 @@ struct SbLds {
   int up[2];                // owner schedule: rows of the applied block staged, by round parity
 };
 
-__device__ __forceinline__ double sb_shr1(double x, double fill) {
+// Row shift by D lanes within each 16-lane row (DPP row_shr:D); the first D
+// lanes of a row take `fill`.
+template <int D>
+__device__ __forceinline__ double sb_shr(double x, double fill) {
   const uint64_t b = __builtin_bit_cast(uint64_t, x);
   const uint64_t f = __builtin_bit_cast(uint64_t, fill);
-  int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)f, (int)(uint32_t)b, 0x111, 0xF, 0xF, false);
-  int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(f >> 32), (int)(uint32_t)(b >> 32), 0x111,
-                                       0xF, 0xF, false);
+  int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)f, (int)(uint32_t)b, 0x110 + D, 0xF, 0xF,
+                                       false);
+  int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(f >> 32), (int)(uint32_t)(b >> 32),
+                                       0x110 + D, 0xF, 0xF, false);
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-__device__ __forceinline__ float sb_shr1(float x, float fill) {
+template <int D>
+__device__ __forceinline__ float sb_shr(float x, float fill) {
   const int b = __builtin_bit_cast(int, x), f = __builtin_bit_cast(int, fill);
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(f, b, 0x111, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(f, b, 0x110 + D, 0xF, 0xF, false));
 }
+
+__device__ __forceinline__ double sb_shr1(double x, double fill) { return sb_shr<1>(x, fill); }
+__device__ __forceinline__ float sb_shr1(float x, float fill) { return sb_shr<1>(x, fill); }
 
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -738,17 +746,25 @@ __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_
 // started (then the launch reports kCodeTimeout and its results are void).
 constexpr int64_t kWaitTicks = 500000000;  // steady-counter ticks (5 s at 100 MHz)
 
-// The owner's apply runs on waves 0-3, one per SIMD: lane g of 16-lane group
-// grp (0..15) applies rotation g of row s - g at sub-step s to the four
-// columns grp + 16 u, so each record read from LDS serves four columns.
+// The owner's apply runs on waves 0-3, one per SIMD.  Lane (q, h, cs) =
+// 16 q + 2 h + cs of those 256 threads applies rotations 2h and 2h+1 of row
+// s - h at sub-step s to the two columns 4 q + 2 cs and 4 q + 2 cs + 1: each
+// pair of records read from LDS serves two columns, the partly rotated L_rj
+// moves to lane h+1 of its column pair with a DPP shift by two lanes (the
+// lanes of h = 0 take the next row of the tile), and the pipeline drains in
+// 7 sub-steps.
 // Wave 4 fetches the records: it waits until a prefix of the next 16 rows
 // has been published, stages those rows in sh.R and announces how far the
 // staged rows go (sh.up, by round parity); the apply waves then run the
 // sub-steps whose rows are all staged, while wave 4 fetches the next rows.
 // Waves 5-7 only pass the rounds' barriers.
-constexpr int kOwnCols = 4;
-constexpr int kOwnGroups = 16;
-constexpr int kOwnThreads = kOwnGroups * 16;  // 256
+constexpr int kOwnCols = 4;       // V values per apply lane: 2 rotations x 2 columns
+constexpr int kOwnThreads = 256;  // apply lanes
+
+// Column u (0, 1) and rotation k (0, 1) of an apply lane; its V value of
+// (rotation 2h + k, column) is w[2 k + u].
+__device__ __forceinline__ int own_col(int tid, int u) { return 4 * (tid >> 4) + 2 * (tid & 1) + u; }
+__device__ __forceinline__ int own_rot(int tid, int k) { return 2 * ((tid & 15) >> 1) + k; }
 
 // Apply block [pb, pb + 64) (tile staged in sh.A, the caller has
 // synchronised) to the owner's columns; w: an apply lane's V values.  next:
@@ -766,48 +782,57 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
   const int kc = KCF ? KCF : kc_;
   const int tid = threadIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int S = kBR + kc - 1;
   if (wv < 4) {
-    const int g = lane & 15, grp = tid >> 4;
-    ST xin[kOwnCols], nxt[kOwnCols];
+    const int h = (lane & 15) >> 1;
+    const int c0 = own_col(tid, 0);
+    const int hf = (kc - 1) >> 1;          // lane holding rotation kc - 1
+    const bool first = (kc & 1) != 0;      // ... as the first of its pair
+    const int S = kBR + hf;                // row 63 reaches lane hf at sub-step 63 + hf
+    ST xin[2], nxt[2];
 #pragma unroll
-    for (int u = 0; u < kOwnCols; ++u) {
-      xin[u] = (ST)sh.A[0][grp + kOwnGroups * u];
-      nxt[u] = (ST)sh.A[1][grp + kOwnGroups * u];
+    for (int u = 0; u < 2; ++u) {
+      xin[u] = (ST)sh.A[0][c0 + u];
+      nxt[u] = (ST)sh.A[1][c0 + u];
     }
-    const RotRec* rp = &sh.R[kPad - g][g];  // record of row s - g at rp[s * kKP]
+    // records of (row s - h, rotations 2h and 2h+1) at rp[s * kKP], rp[s * kKP + 1]
+    const RotRec* rp = &sh.R[kPad - h][2 * h];
     int s = 0;
     for (int rd = 0;; ++rd) {
       __syncthreads();
       const int up = sh.up[rd & 1];
-      const int lim = up >= kBR ? S : up;  // rows <= s - g < up are staged
-      RotRec cf = rp[s * kKP];
+      const int lim = up >= kBR ? S : up;  // rows <= s - h < up are staged
+      RotRec q0 = rp[s * kKP], q1 = rp[s * kKP + 1];
       for (; s < lim; ++s) {
-        const int r = s - g;
-        const RotRec cfn = rp[imin(s + 1, kBR + kKP - 1 + g) * kKP];  // row <= 79
-        ST nxt2[kOwnCols];
-        if (g == 0) {
+        const int r = s - h;
+        // s + 1 <= S <= 71: record rows up to 87
+        const RotRec n0 = rp[(s + 1) * kKP], n1 = rp[(s + 1) * kKP + 1];
+        ST nxt2[2];
+        if (h == 0) {
           const int rn2 = imin(s + 2, kBR - 1);
 #pragma unroll
-          for (int u = 0; u < kOwnCols; ++u) nxt2[u] = (ST)sh.A[rn2][grp + kOwnGroups * u];
+          for (int u = 0; u < 2; ++u) nxt2[u] = (ST)sh.A[rn2][c0 + u];
         }
-        const ST c = (ST)cf.c, sn = (ST)cf.s, ic = (ST)cf.ic;
-        ST x[kOwnCols];
+        const ST ca = (ST)q0.c, sa = (ST)q0.s, ia = (ST)q0.ic;
+        const ST cb = (ST)q1.c, sb = (ST)q1.s, ib = (ST)q1.ic;
+        ST x1[2], x2[2];
 #pragma unroll
-        for (int u = 0; u < kOwnCols; ++u) {
-          x[u] = fma_t((ST)SG * sn, w[u], xin[u]) * ic;
-          w[u] = fma_t(-sn, x[u], c * w[u]);
+        for (int u = 0; u < 2; ++u) {
+          x1[u] = fma_t((ST)SG * sa, w[u], xin[u]) * ia;
+          w[u] = fma_t(-sa, x1[u], ca * w[u]);
+          x2[u] = fma_t((ST)SG * sb, w[2 + u], x1[u]) * ib;
+          w[2 + u] = fma_t(-sb, x2[u], cb * w[2 + u]);
         }
-        if (g == kc - 1 && r >= 0 && r < kBR) {
+        if (h == hf && r >= 0 && r < kBR) {
 #pragma unroll
-          for (int u = 0; u < kOwnCols; ++u) sh.A[r][grp + kOwnGroups * u] = x[u];
+          for (int u = 0; u < 2; ++u) sh.A[r][c0 + u] = first ? x1[u] : x2[u];
         }
 #pragma unroll
-        for (int u = 0; u < kOwnCols; ++u) {
-          xin[u] = sb_shr1(x[u], nxt[u]);
+        for (int u = 0; u < 2; ++u) {
+          xin[u] = sb_shr<2>(x2[u], nxt[u]);
           nxt[u] = nxt2[u];
         }
-        cf = cfn;
+        q0 = n0;
+        q1 = n1;
       }
       if (up >= kBR) break;
     }
@@ -909,13 +934,14 @@ __global__ __launch_bounds__(kThreads) void k_sb_owner(
     const int idx = tid + q * kThreads, i = idx >> 6, c = idx & 63;
     lt[q] = (i < bbc && c < bbc && c >= i) ? L[(pj + i) * ldl + pj + c] : (ST)0;
   }
-  const int g = tid & 15, grp = tid >> 4;
   ST w[kOwnCols];
 #pragma unroll
-  for (int u = 0; u < kOwnCols; ++u) {
-    const int c = grp + kOwnGroups * u;
-    w[u] = (tid < kOwnThreads && c < bbc && g < kc) ? W[(pj + c) * ldw + g] : (ST)0;
-  }
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int c = own_col(tid, u), m = own_rot(tid, k);
+      w[2 * k + u] = (tid < kOwnThreads && c < bbc && m < kc) ? W[(pj + c) * ldw + m] : (ST)0;
+    }
   TileRegs<ST> tr;
   if (j > 0) tile_issue_a(tr, L, ldl, 0, pj, bbc);
 #pragma unroll
@@ -943,12 +969,14 @@ __global__ __launch_bounds__(kThreads) void k_sb_owner(
     }
   }
   // V of the block's columns, after all earlier rows, starts the chain
-  if (tid < kOwnThreads && g < kc) {
+  if (tid < kOwnThreads) {
 #pragma unroll
-    for (int u = 0; u < kOwnCols; ++u) {
-      const int c = grp + kOwnGroups * u;
-      sh.Hb[g][1][c] = c < bbc ? (double)w[u] : 0.0;
-    }
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int c = own_col(tid, u), m = own_rot(tid, k);
+        if (m < kc) sh.Hb[m][1][c] = c < bbc ? (double)w[2 * k + u] : 0.0;
+      }
   }
   if (bbc < kBR) chain_setup_records(sh);
   __syncthreads();
