@@ -103,12 +103,14 @@ struct Fill {
 };
 
 struct SbLds {
+  // first, so that every record is within the 64 KB reach of an LDS
+  // instruction's immediate offset from a lane's base address
+  RotRec R[kRRows][kKP];    // records by row + 16: identity / block rows / identity
   double Lb[kBR][kBR + 1];  // the block's original upper triangle
   union {
     double A[kBR][kBR + 4];      // apply tile: rows of block b-1 x 64 columns
     double Lh[kPad + kBR][kBR];  // helper results after the last rotation, rows -16..63
   };
-  RotRec R[kRRows][kKP];    // records by row + 16: identity / block rows / identity
   double Hb[kKP][2][kBR];   // V_j[m] after each helper rotation, by step parity
   double X[5][2][kBR];      // helper h -> h+1, by step parity
   Band Lc[kRRows];          // wave 0 results by row + 16
@@ -796,43 +798,53 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
     }
     // records of (row s - h, rotations 2h and 2h+1) at rp[s * kKP], rp[s * kKP + 1]
     const RotRec* rp = &sh.R[kPad - h][2 * h];
+    // one sub-step: records qc (row s - h), the row entering lane h = 0 at
+    // the next sub-step in fc; loads the next records into qn and the row
+    // after into fn.  Called with the two register sets alternating.
+    auto step = [&](int s, const RotRec (&qc)[2], RotRec (&qn)[2], const ST (&fc)[2],
+                    ST (&fn)[2]) {
+      const int r = s - h;
+      // s + 1 <= S <= 71: record rows up to 87
+      qn[0] = rp[(s + 1) * kKP];
+      qn[1] = rp[(s + 1) * kKP + 1];
+      if (h == 0) {
+        const int rn2 = imin(s + 2, kBR - 1);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) fn[u] = (ST)sh.A[rn2][c0 + u];
+      }
+      const ST ca = (ST)qc[0].c, sa = (ST)qc[0].s, ia = (ST)qc[0].ic;
+      const ST cb = (ST)qc[1].c, sb = (ST)qc[1].s, ib = (ST)qc[1].ic;
+      ST x1[2], x2[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        x1[u] = fma_t((ST)SG * sa, w[u], xin[u]) * ia;
+        w[u] = fma_t(-sa, x1[u], ca * w[u]);
+        x2[u] = fma_t((ST)SG * sb, w[2 + u], x1[u]) * ib;
+        w[2 + u] = fma_t(-sb, x2[u], cb * w[2 + u]);
+      }
+      if (h == hf && r >= 0 && r < kBR) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) sh.A[r][c0 + u] = first ? x1[u] : x2[u];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) xin[u] = sb_shr<2>(x2[u], fc[u]);
+    };
     int s = 0;
+    ST fa[2] = {nxt[0], nxt[1]}, fb[2] = {(ST)0, (ST)0};  // only lanes h = 0 use them
     for (int rd = 0;; ++rd) {
       __syncthreads();
       const int up = sh.up[rd & 1];
       const int lim = up >= kBR ? S : up;  // rows <= s - h < up are staged
-      RotRec q0 = rp[s * kKP], q1 = rp[s * kKP + 1];
-      for (; s < lim; ++s) {
-        const int r = s - h;
-        // s + 1 <= S <= 71: record rows up to 87
-        const RotRec n0 = rp[(s + 1) * kKP], n1 = rp[(s + 1) * kKP + 1];
-        ST nxt2[2];
-        if (h == 0) {
-          const int rn2 = imin(s + 2, kBR - 1);
-#pragma unroll
-          for (int u = 0; u < 2; ++u) nxt2[u] = (ST)sh.A[rn2][c0 + u];
-        }
-        const ST ca = (ST)q0.c, sa = (ST)q0.s, ia = (ST)q0.ic;
-        const ST cb = (ST)q1.c, sb = (ST)q1.s, ib = (ST)q1.ic;
-        ST x1[2], x2[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          x1[u] = fma_t((ST)SG * sa, w[u], xin[u]) * ia;
-          w[u] = fma_t(-sa, x1[u], ca * w[u]);
-          x2[u] = fma_t((ST)SG * sb, w[2 + u], x1[u]) * ib;
-          w[2 + u] = fma_t(-sb, x2[u], cb * w[2 + u]);
-        }
-        if (h == hf && r >= 0 && r < kBR) {
-#pragma unroll
-          for (int u = 0; u < 2; ++u) sh.A[r][c0 + u] = first ? x1[u] : x2[u];
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          xin[u] = sb_shr<2>(x2[u], nxt[u]);
-          nxt[u] = nxt2[u];
-        }
-        q0 = n0;
-        q1 = n1;
+      RotRec qa[2] = {rp[s * kKP], rp[s * kKP + 1]}, qb[2];
+      for (; s + 2 <= lim; s += 2) {
+        step(s, qa, qb, fa, fb);
+        step(s + 1, qb, qa, fb, fa);
+      }
+      if (s < lim) {
+        step(s, qa, qb, fa, fb);
+        ++s;
+        fa[0] = fb[0];
+        fa[1] = fb[1];
       }
       if (up >= kBR) break;
     }

@@ -210,13 +210,32 @@ def test_sync_entry_point_and_python_errors(orc):
     (1500, 2, -1), (2049, 16, -1),
 ])
 def test_chain_schedule_equals_row_schedule_bitwise(orc, n, k, sigma):
-    """The default fast schedule (64-row blocks run as a systolic chain in one
-    workgroup, then a column-parallel Apply) and the per-row fast schedule run
-    the same Compute/Apply arithmetic in the same per-element order: their
-    results must be identical bit for bit."""
+    """The default fast schedule (the owner schedule: 64-row blocks, each run
+    as a systolic chain by the workgroup owning its columns, which has applied
+    the earlier blocks to them) and the per-row fast schedule run the same
+    Compute/Apply arithmetic in the same per-element order: their results must
+    be identical bit for bit (k <= 16: one pass in both)."""
     print_case("schedules", n=n, k=k, sigma=sigma)
     L, V = inputs_for(orc, n, k, 3000 + n + k, sigma)
     a, sa, _, _ = run_gpu(L, V, sigma)
     b, sb, _, _ = run_gpu(L, V, sigma, blocked=True)
     assert sa == 0 and sb == 0
     assert np.array_equal(a, b), "max |diff| = %g" % np.abs(a - b).max()
+
+
+@pytest.mark.parametrize("n,k,sigma", [(300, 33, 1), (200, 21, -1), (130, 47, 1)])
+def test_passes_equal_consecutive_column_slices_bitwise(orc, n, k, sigma):
+    """k > 16 runs in passes of 16 columns of V; pass p only rotates its own
+    columns of the private copy of V, so one call equals consecutive calls on
+    the 16-column slices of V, bit for bit (the last slice narrower)."""
+    print_case("passes", n=n, k=k, sigma=sigma)
+    L, V = inputs_for(orc, n, k, 3100 + n + k, sigma)
+    a, sa, _, _ = run_gpu(L, V, sigma)
+    assert sa == 0
+    b = L.copy()
+    for m0 in range(0, k, 16):
+        b, sb, _, _ = run_gpu(b, np.ascontiguousarray(V[:, m0:m0 + 16]), sigma)
+        assert sb == 0
+    assert np.array_equal(a, b), "max |diff| = %g" % np.abs(a - b).max()
+    ref, st, _ = orc.modify(L, V, sigma)
+    assert st == 0 and rel_diff(a, ref) <= RESID_TOL
