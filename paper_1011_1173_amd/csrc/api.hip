@@ -295,7 +295,8 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P)
       e.bbc = (int32_t)std::min(kBlock, d.n - e.pc);
       e.kc = (int32_t)std::min(kPass, d.k - e.m0);
       e.rest0 = (int32_t)rest;
-      rest += e.pa >= 0 ? ceil_div(d.n - e.pc - e.bbc, kBlock) : 0;
+      // rest workgroups apply two 64-column tiles each
+      rest += e.pa >= 0 ? ceil_div(ceil_div(d.n - e.pc - e.bbc, kBlock), 2) : 0;
       P->ent.push_back(e);
     }
     S.nent = (int64_t)P->ent.size() - S.off;

@@ -26,14 +26,15 @@ struct BatchEntry {
   int32_t f;       // factor index
   int32_t bbc;     // rows of the block
   int32_t kc;      // columns of V in this pass
-  int32_t rest0;   // index of the entry's first rest tile among the step's rest tiles
+  int32_t rest0;   // index of the entry's first rest workgroup among the step's
+                   // (a rest workgroup applies two 64-column tiles)
 };
 
 // Host-side description of one launch.
 struct BatchStep {
   int64_t off;     // first entry
   int64_t nent;    // entries (= chain workgroups)
-  int64_t nrest;   // rest tiles
+  int64_t nrest;   // rest workgroups
 };
 
 }  // namespace chm

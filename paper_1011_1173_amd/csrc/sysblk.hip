@@ -106,7 +106,10 @@ struct SbLds {
   // first, so that every record is within the 64 KB reach of an LDS
   // instruction's immediate offset from a lane's base address
   RotRec R[kRRows][kKP];    // records by row + 16: identity / block rows / identity
-  double Lb[kBR][kBR + 1];  // the block's original upper triangle
+  union {
+    double Lb[kBR][kBR + 1];  // chain: the block's original upper triangle
+    double A2[kBR][kBR + 1];  // batch rest workgroups: their second apply tile
+  };
   union {
     double A[kBR][kBR + 4];      // apply tile: rows of block b-1 x 64 columns
     double Lh[kPad + kBR][kBR];  // helper results after the last rotation, rows -16..63
@@ -162,7 +165,6 @@ __device__ __forceinline__ RotRec identity_rec() {
 // the loads cost one memory round trip instead of one per loop iteration.
 constexpr int kRecPerThread = kRRows * kKP / kThreads;  // 3
 constexpr int kTilePerThread = kBR * kBR / kThreads;    // 8
-constexpr int kColsPerLane = kBR * kKP / kThreads;      // 2 columns per lane in an apply tile
 
 // Records of rows [p, p + rows) (columns m < kc) at row offset kPad, identity
 // records everywhere else.
@@ -195,14 +197,11 @@ __device__ __forceinline__ void records_stage(SbLds& sh, const RecRegs<ST>& rg) 
   }
 }
 
-// An apply tile: rows [pa, pa + 64) x columns [j0, j0 + ncols) of L, and the
-// V values of this thread's columns (lane g of group grp: columns
-// grp + 32 q, column g of V).
-constexpr int kGroups = kThreads / 16;
+// An apply tile: rows [pa, pa + 64) x columns [j0, j0 + ncols) of L, loaded
+// by all threads of the workgroup.
 template <typename ST>
 struct TileRegs {
   ST a[kTilePerThread];
-  ST w[kColsPerLane];
 };
 
 template <typename ST>
@@ -213,19 +212,6 @@ __device__ __forceinline__ void tile_issue_a(TileRegs<ST>& tr, const ST* __restr
   for (int q = 0; q < kTilePerThread; ++q) {
     const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
     tr.a[q] = c < ncols ? L[(pa + r) * ldl + j0 + c] : (ST)0;
-  }
-}
-
-template <typename ST>
-__device__ __forceinline__ void tile_issue(TileRegs<ST>& tr, const ST* __restrict__ L, int64_t ldl,
-                                           const ST* __restrict__ W, int64_t ldw, int kc,
-                                           int64_t pa, int64_t j0, int ncols) {
-  tile_issue_a(tr, L, ldl, pa, j0, ncols);
-  const int g = threadIdx.x & 15, grp = threadIdx.x >> 4;
-#pragma unroll
-  for (int q = 0; q < kColsPerLane; ++q) {
-    const int c = grp + kGroups * q;
-    tr.w[q] = (c < ncols && g < kc) ? W[(j0 + c) * ldw + g] : (ST)0;
   }
 }
 
@@ -271,81 +257,98 @@ __device__ __forceinline__ void publish_record(GRec<ST>* dst, const RotRec& r) {
   __hip_atomic_store(&dst->ic, (ST)r.ic, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Apply the records in sh.R (rows [pa, pa + 64)) to columns [j0, j0 + ncols)
-// of the tile staged in sh.A, with this thread's V values w.  HEAD: V of
-// those columns goes to sh.Hb parity 1 (the chain's initial values);
-// otherwise back to W.  The caller has staged sh.R and sh.A and
-// synchronised.  The arithmetic runs in the storage type ST (the records
-// hold ST values).
-template <bool HEAD, int SG, typename ST, int KCF>
-__device__ __forceinline__ void apply_tile(SbLds& sh, ST* __restrict__ L, int64_t ldl,
-                                           ST* __restrict__ W, int64_t ldw, int kc_,
-                                           int64_t pa, int64_t j0, int ncols,
-                                           const ST (&w0)[kColsPerLane]) {
-  constexpr int NQ = kColsPerLane;
+// The Apply of a block to a tile of 64 columns runs on 256 threads (four
+// waves, one per SIMD).  Lane (q, h, cs) = 16 q + 2 h + cs applies rotations
+// 2h and 2h+1 of row s - h at sub-step s to the two columns 4 q + 2 cs and
+// 4 q + 2 cs + 1: each pair of records read from LDS serves two columns, the
+// partly rotated L_rj moves to lane h+1 of its column pair with a DPP shift
+// by two lanes (the lanes of h = 0 take the next row of the tile), V_j[m]
+// stays in a register, and the pipeline drains in 7 sub-steps.  The lane
+// holding rotation kc - 1 leaves the final value in the tile.
+constexpr int kOwnCols = 4;       // V values per apply lane: 2 rotations x 2 columns
+constexpr int kOwnThreads = 256;  // apply lanes
+
+// Column u (0, 1) and rotation k (0, 1) of apply lane lt; its V value of
+// (rotation 2h + k, column) is w[2 k + u].
+__device__ __forceinline__ int own_col(int lt, int u) { return 4 * (lt >> 4) + 2 * (lt & 1) + u; }
+__device__ __forceinline__ int own_rot(int lt, int k) { return 2 * ((lt & 15) >> 1) + k; }
+
+// V of apply lane lt's columns [j0, j0 + ncols), columns m < kc of V.
+template <typename ST>
+__device__ __forceinline__ void w2x2_load(ST (&w)[kOwnCols], const ST* __restrict__ W,
+                                          int64_t ldw, int kc, int64_t j0, int ncols, int lt) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int c = own_col(lt, u), m = own_rot(lt, k);
+      w[2 * k + u] = (c < ncols && m < kc) ? W[(j0 + c) * ldw + m] : (ST)0;
+    }
+}
+
+// One sub-step s of an apply lane: records qc (row s - h), the row that
+// enters the lanes of h = 0 at the next sub-step in fc; loads the next
+// records into qn and the row after into fn.  The tile is in LDS at `tile`
+// with row stride LD.  Callers alternate two register sets, so that nothing
+// is copied between sub-steps.
+template <int SG, typename ST, int LD>
+__device__ __forceinline__ void sub2x2(const double* tile_in, double* tile, const RotRec* rp,
+                                       int s, int h, int c0, int hf, bool first,
+                                       ST (&w)[kOwnCols], ST (&xin)[2], const RotRec (&qc)[2],
+                                       RotRec (&qn)[2], const ST (&fc)[2], ST (&fn)[2]) {
+  const int r = s - h;
+  // s + 1 <= 71: record rows up to 87
+  qn[0] = rp[(s + 1) * kKP];
+  qn[1] = rp[(s + 1) * kKP + 1];
+  if (h == 0) {
+    const int rn2 = imin(s + 2, kBR - 1);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) fn[u] = (ST)tile_in[rn2 * LD + c0 + u];
+  }
+  const ST ca = (ST)qc[0].c, sa = (ST)qc[0].s, ia = (ST)qc[0].ic;
+  const ST cb = (ST)qc[1].c, sb = (ST)qc[1].s, ib = (ST)qc[1].ic;
+  ST x1[2], x2[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    x1[u] = fma_t((ST)SG * sa, w[u], xin[u]) * ia;
+    w[u] = fma_t(-sa, x1[u], ca * w[u]);
+    x2[u] = fma_t((ST)SG * sb, w[2 + u], x1[u]) * ib;
+    w[2 + u] = fma_t(-sb, x2[u], cb * w[2 + u]);
+  }
+  if (h == hf && r >= 0 && r < kBR) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) tile[r * LD + c0 + u] = first ? x1[u] : x2[u];
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) xin[u] = sb_shr<2>(x2[u], fc[u]);
+}
+
+// Apply the records staged in sh.R (the block's 64 rows, identity records
+// around them) to the 64 x 64 tile at `tile` (row stride LD), as apply lane
+// lt of one half of the workgroup.  No barrier inside.  The arithmetic runs
+// in the storage type ST (the records hold ST values).
+template <int SG, typename ST, int KCF, int LD>
+__device__ __forceinline__ void apply2x2(SbLds& sh, double* tile, int kc_, int lt,
+                                         ST (&w)[kOwnCols]) {
   const int kc = KCF ? KCF : kc_;
-  const int tid = threadIdx.x;
-  const int g = tid & 15, grp = tid >> 4;  // lane g of group grp: columns grp + 32 q
-  ST w[NQ];
+  const int h = (lt & 15) >> 1, c0 = own_col(lt, 0);
+  const int hf = (kc - 1) >> 1;      // lane holding rotation kc - 1
+  const bool first = (kc & 1) != 0;  // ... as the first of its pair
+  const int S = kBR + hf;            // row 63 reaches lane hf at sub-step 63 + hf
+  ST xin[2], fa[2], fb[2] = {(ST)0, (ST)0};
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) w[q] = w0[q];
-  // xin: lane 0 of a group takes row s of the tile, lane g > 0 the value
-  // lane g-1 produced at sub-step s-1 (the DPP shift's fill is the next row,
-  // which only lane 0 reads).  The record and the tile row of sub-step s+1
-  // are read during sub-step s (a tile row is read before lane kc-1
-  // overwrites it with its final value: row s+2 is read at sub-step s,
-  // final at sub-step s+1+kc).
-  ST xin[NQ], nxt[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    xin[q] = (ST)sh.A[0][grp + kGroups * q];
-    nxt[q] = (ST)sh.A[1][grp + kGroups * q];
+  for (int u = 0; u < 2; ++u) {
+    xin[u] = (ST)tile[c0 + u];
+    fa[u] = (ST)tile[LD + c0 + u];
   }
-  const RotRec* rp = &sh.R[kPad - g][g];  // record of row s - g at rp[s * kKP]
-  RotRec cf = rp[0];
-  const int S = kBR + kc - 1;
-  for (int s = 0; s < S; ++s) {
-    const int r = s - g;
-    const RotRec cfn = rp[imin(s + 1, kBR + kKP - 1 + g) * kKP];  // row <= 79
-    ST nxt2[NQ];
-    if (g == 0) {
-      const int rn2 = imin(s + 2, kBR - 1);
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) nxt2[q] = (ST)sh.A[rn2][grp + kGroups * q];
-    }
-    const ST c = (ST)cf.c, sn = (ST)cf.s, ic = (ST)cf.ic;
-    ST x[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      x[q] = fma_t((ST)SG * sn, w[q], xin[q]) * ic;
-      w[q] = fma_t(-sn, x[q], c * w[q]);
-    }
-    if (g == kc - 1 && r >= 0 && r < kBR) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) sh.A[r][grp + kGroups * q] = x[q];
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      xin[q] = sb_shr1(x[q], nxt[q]);
-      nxt[q] = nxt2[q];
-    }
-    cf = cfn;
+  const RotRec* rp = &sh.R[kPad - h][2 * h];
+  RotRec qa[2] = {rp[0], rp[1]}, qb[2];
+  int s = 0;
+  for (; s + 2 <= S; s += 2) {
+    sub2x2<SG, ST, LD>(tile, tile, rp, s, h, c0, hf, first, w, xin, qa, qb, fa, fb);
+    sub2x2<SG, ST, LD>(tile, tile, rp, s + 1, h, c0, hf, first, w, xin, qb, qa, fb, fa);
   }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kTilePerThread; ++q) {
-    const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
-    if (c < ncols) L[(pa + r) * ldl + j0 + c] = (ST)sh.A[r][c];
-  }
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int c = grp + kGroups * q;
-    if (HEAD) {
-      if (g < kc) sh.Hb[g][1][c] = (double)w[q];
-    } else {
-      if (c < ncols && g < kc) W[(j0 + c) * ldw + g] = w[q];
-    }
-  }
+  if (s < S) sub2x2<SG, ST, LD>(tile, tile, rp, s, h, c0, hf, first, w, xin, qa, qb, fa, fb);
 }
 
 // ------------------------------------------------------------------ chain
@@ -633,9 +636,10 @@ __device__ __forceinline__ void chain_finish(SbLds& sh, ST* __restrict__ L, int6
 
 // ------------------------------------------------------- launch per block
 // Batched factors run one launch per step: workgroup 0 applies block b-1 to
-// the columns of block b (the head tile), then runs the chain of block b and
-// writes its records for the next launch; the other workgroups apply block
-// b-1 to the 64-column tiles right of block b.
+// the columns of block b (the head tile, on waves 0-3), then runs the chain
+// of block b and writes its records for the next launch; each other
+// workgroup applies block b-1 to two of the 64-column tiles right of block
+// b, one per half of its waves.
 template <int SG, typename ST, int KCF>
 __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t ldl,
                                          ST* __restrict__ W, int64_t ldw, int kc_,
@@ -652,7 +656,11 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
   RecRegs<ST> rg;
   records_issue(rg, T, pa, hrows, kc);  // all identity without a head tile
   TileRegs<ST> tr;
-  if (head) tile_issue(tr, L, ldl, W, ldw, kc, pa, pc, bbc);
+  ST wa[kOwnCols];
+  if (head) {
+    tile_issue_a(tr, L, ldl, pa, pc, bbc);
+    if (tid < kOwnThreads) w2x2_load(wa, W, ldw, kc, pc, bbc, tid);
+  }
   constexpr int kHbPerThread = kBR * kKP / kThreads;  // 2
   ST lt[kTilePerThread], wh[kHbPerThread];
   if (chain) {
@@ -686,7 +694,25 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
     }
   }
   __syncthreads();
-  if (head) apply_tile<true, SG, ST, KCF>(sh, L, ldl, W, ldw, kc, pa, pc, bbc, tr.w);
+  if (head) {
+    if (tid < kOwnThreads) apply2x2<SG, ST, KCF, kBR + 4>(sh, &sh.A[0][0], kc, tid, wa);
+    __syncthreads();
+    // the head tile's final values, and V of block b's columns for the chain
+#pragma unroll
+    for (int q = 0; q < kTilePerThread; ++q) {
+      const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
+      if (c < bbc) L[(pa + r) * ldl + pc + c] = (ST)sh.A[r][c];
+    }
+    if (tid < kOwnThreads) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int m = own_rot(tid, k);
+          if (m < kc) sh.Hb[m][1][own_col(tid, u)] = (double)wa[2 * k + u];
+        }
+    }
+  }
   if (!chain) return;
   __syncthreads();
   chain_setup(sh, bbc);
@@ -705,8 +731,9 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
 }
 
 // One workgroup's share of the launch for block [pc, pc + bbc) of one factor:
-// wg == 0 runs the chain, wg >= 1 applies block [pa, pa + 64) to the tiles
-// right of block b.
+// wg == 0 runs the chain, wg >= 1 applies block [pa, pa + 64) to tiles
+// 2 (wg - 1) and 2 (wg - 1) + 1 right of block b (waves 0-3 the first, in
+// sh.A, waves 4-7 the second, in sh.A2).
 template <int SG, typename ST, int KCF>
 __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_t ldl,
                                            ST* __restrict__ W, int64_t ldw, int kc,
@@ -724,16 +751,48 @@ __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_
                           lim);
   } else {
     if (pa < 0 || pa >= lim) return;
-    const int64_t j0 = pc + bbc + (int64_t)(wg - 1) * kBR;
-    const int ncols = n - j0 < kBR ? (int)(n - j0) : kBR;
+    const int tid = threadIdx.x, half = tid >> 8, lt = tid & (kOwnThreads - 1);
+    const int64_t j0 = pc + bbc + (int64_t)(2 * (wg - 1) + half) * kBR;
+    const int ncols = j0 < n ? (n - j0 < kBR ? (int)(n - j0) : kBR) : 0;
     RecRegs<ST> rg;
     records_issue(rg, T, pa, lim - pa < kBR ? (int)(lim - pa) : kBR, kc);
-    TileRegs<ST> tr;
-    tile_issue(tr, L, ldl, W, ldw, kc, pa, j0, ncols);
+    constexpr int kHalfTile = kBR * kBR / kOwnThreads;  // 16 elements per thread
+    ST ta[kHalfTile];
+#pragma unroll
+    for (int q = 0; q < kHalfTile; ++q) {
+      const int idx = lt + q * kOwnThreads, r = idx >> 6, c = idx & 63;
+      ta[q] = c < ncols ? L[(pa + r) * ldl + j0 + c] : (ST)0;
+    }
+    ST wa[kOwnCols];
+    w2x2_load(wa, W, ldw, kc, j0, ncols, lt);
     records_stage(sh, rg);
-    tile_stage(sh, tr);
+    double* const tile = half ? &sh.A2[0][0] : &sh.A[0][0];
+    const int ld = half ? kBR + 1 : kBR + 4;
+#pragma unroll
+    for (int q = 0; q < kHalfTile; ++q) {
+      const int idx = lt + q * kOwnThreads;
+      tile[(idx >> 6) * ld + (idx & 63)] = (double)ta[q];
+    }
     __syncthreads();
-    apply_tile<false, SG, ST, KCF>(sh, L, ldl, W, ldw, kc, pa, j0, ncols, tr.w);
+    if (ncols > 0) {
+      if (half) apply2x2<SG, ST, KCF, kBR + 1>(sh, &sh.A2[0][0], kc, lt, wa);
+      else apply2x2<SG, ST, KCF, kBR + 4>(sh, &sh.A[0][0], kc, lt, wa);
+    }
+    __syncthreads();
+    if (ncols > 0) {
+#pragma unroll
+      for (int q = 0; q < kHalfTile; ++q) {
+        const int idx = lt + q * kOwnThreads, r = idx >> 6, c = idx & 63;
+        if (c < ncols) L[(pa + r) * ldl + j0 + c] = (ST)tile[r * ld + c];
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int c = own_col(lt, u), m = own_rot(lt, k);
+          if (c < ncols && m < kc) W[(j0 + c) * ldw + m] = wa[2 * k + u];
+        }
+    }
   }
 }
 
@@ -760,13 +819,6 @@ constexpr int64_t kWaitTicks = 500000000;  // steady-counter ticks (5 s at 100 M
 // staged rows go (sh.up, by round parity); the apply waves then run the
 // sub-steps whose rows are all staged, while wave 4 fetches the next rows.
 // Waves 5-7 only pass the rounds' barriers.
-constexpr int kOwnCols = 4;       // V values per apply lane: 2 rotations x 2 columns
-constexpr int kOwnThreads = 256;  // apply lanes
-
-// Column u (0, 1) and rotation k (0, 1) of an apply lane; its V value of
-// (rotation 2h + k, column) is w[2 k + u].
-__device__ __forceinline__ int own_col(int tid, int u) { return 4 * (tid >> 4) + 2 * (tid & 1) + u; }
-__device__ __forceinline__ int own_rot(int tid, int k) { return 2 * ((tid & 15) >> 1) + k; }
 
 // Apply block [pb, pb + 64) (tile staged in sh.A, the caller has
 // synchronised) to the owner's columns; w: an apply lane's V values.  next:
@@ -790,58 +842,28 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
     const int hf = (kc - 1) >> 1;          // lane holding rotation kc - 1
     const bool first = (kc & 1) != 0;      // ... as the first of its pair
     const int S = kBR + hf;                // row 63 reaches lane hf at sub-step 63 + hf
-    ST xin[2], nxt[2];
+    double* const tile = &sh.A[0][0];
+    constexpr int LD = kBR + 4;
+    ST xin[2], fa[2], fb[2] = {(ST)0, (ST)0};  // fa, fb: only lanes h = 0 use them
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      xin[u] = (ST)sh.A[0][c0 + u];
-      nxt[u] = (ST)sh.A[1][c0 + u];
+      xin[u] = (ST)tile[c0 + u];
+      fa[u] = (ST)tile[LD + c0 + u];
     }
     // records of (row s - h, rotations 2h and 2h+1) at rp[s * kKP], rp[s * kKP + 1]
     const RotRec* rp = &sh.R[kPad - h][2 * h];
-    // one sub-step: records qc (row s - h), the row entering lane h = 0 at
-    // the next sub-step in fc; loads the next records into qn and the row
-    // after into fn.  Called with the two register sets alternating.
-    auto step = [&](int s, const RotRec (&qc)[2], RotRec (&qn)[2], const ST (&fc)[2],
-                    ST (&fn)[2]) {
-      const int r = s - h;
-      // s + 1 <= S <= 71: record rows up to 87
-      qn[0] = rp[(s + 1) * kKP];
-      qn[1] = rp[(s + 1) * kKP + 1];
-      if (h == 0) {
-        const int rn2 = imin(s + 2, kBR - 1);
-#pragma unroll
-        for (int u = 0; u < 2; ++u) fn[u] = (ST)sh.A[rn2][c0 + u];
-      }
-      const ST ca = (ST)qc[0].c, sa = (ST)qc[0].s, ia = (ST)qc[0].ic;
-      const ST cb = (ST)qc[1].c, sb = (ST)qc[1].s, ib = (ST)qc[1].ic;
-      ST x1[2], x2[2];
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        x1[u] = fma_t((ST)SG * sa, w[u], xin[u]) * ia;
-        w[u] = fma_t(-sa, x1[u], ca * w[u]);
-        x2[u] = fma_t((ST)SG * sb, w[2 + u], x1[u]) * ib;
-        w[2 + u] = fma_t(-sb, x2[u], cb * w[2 + u]);
-      }
-      if (h == hf && r >= 0 && r < kBR) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u) sh.A[r][c0 + u] = first ? x1[u] : x2[u];
-      }
-#pragma unroll
-      for (int u = 0; u < 2; ++u) xin[u] = sb_shr<2>(x2[u], fc[u]);
-    };
     int s = 0;
-    ST fa[2] = {nxt[0], nxt[1]}, fb[2] = {(ST)0, (ST)0};  // only lanes h = 0 use them
     for (int rd = 0;; ++rd) {
       __syncthreads();
       const int up = sh.up[rd & 1];
       const int lim = up >= kBR ? S : up;  // rows <= s - h < up are staged
       RotRec qa[2] = {rp[s * kKP], rp[s * kKP + 1]}, qb[2];
       for (; s + 2 <= lim; s += 2) {
-        step(s, qa, qb, fa, fb);
-        step(s + 1, qb, qa, fb, fa);
+        sub2x2<SG, ST, LD>(tile, tile, rp, s, h, c0, hf, first, w, xin, qa, qb, fa, fb);
+        sub2x2<SG, ST, LD>(tile, tile, rp, s + 1, h, c0, hf, first, w, xin, qb, qa, fb, fa);
       }
       if (s < lim) {
-        step(s, qa, qb, fa, fb);
+        sub2x2<SG, ST, LD>(tile, tile, rp, s, h, c0, hf, first, w, xin, qa, qb, fa, fb);
         ++s;
         fa[0] = fb[0];
         fa[1] = fb[1];
@@ -1011,7 +1033,7 @@ __global__ void k_owner_clear(GRec<ST>* __restrict__ T, int64_t words) {
 
 // Batched form: the launch of step s holds, for every factor with more than
 // s steps, the chain workgroup of its step s (workgroups [0, nent), longest
-// factor first) and then all their rest tiles.
+// factor first) and then all their rest workgroups.
 __global__ __launch_bounds__(kThreads) void k_sb_batch(const BatchFactor* __restrict__ fac,
                                                        const BatchEntry* __restrict__ ent,
                                                        int nent) {
@@ -1019,7 +1041,7 @@ __global__ __launch_bounds__(kThreads) void k_sb_batch(const BatchFactor* __rest
   const int x = (int)blockIdx.x;
   int e = x, wg = 0;
   if (x >= nent) {
-    const int r = x - nent;  // rest tile r of the step: largest e with ent[e].rest0 <= r
+    const int r = x - nent;  // rest workgroup r of the step: largest e with ent[e].rest0 <= r
     int lo = 0, hi = nent - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
