@@ -53,10 +53,12 @@ def parse():
     ap.add_argument("--n", type=int, default=5000)
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--mode", choices=["headline", "batched", "served"], default="headline",
+    ap.add_argument("--mode", choices=["headline", "batched", "served", "sweep"],
+                    default="headline",
                     help="headline: one factor, n=5000, k=16 (default); batched: 256 factors "
                          "of uneven size per call; served: a pool of factors fed by Poisson "
-                         "arrivals through the served mode")
+                         "arrivals through the served mode; sweep: single factors with n in "
+                         "{1e4, 2e4, 4e4}, k in {1, 16, 64}, FP64 and FP32 storage")
     ap.add_argument("--batch-dtype", choices=["f64", "f32s"], default="f64",
                     help="batched mode: storage type of the factors")
     ap.add_argument("--served-seconds", type=float, default=3.0,
@@ -143,6 +145,7 @@ def batched(args):
 
     stream = torch.cuda.Stream()
     batches = [make_batch() for _ in range(args.warmup + args.steps)]
+    torch.cuda.synchronize()  # the V's were written on the default stream
     ws = None
     times, byts = [], []
     for i, (Vs, sg) in enumerate(batches):
@@ -168,6 +171,66 @@ def batched(args):
                       "dense_GB": sum(es * n * n for n in ns) / 1e9},
            "batch_ms": {"median": med, "min": ts[0], "max": ts[-1]},
            "effective_GBps": (sum(byts) / len(byts)) / (med * 1e-3) / 1e9}
+    print(json.dumps(out))
+    return 0
+
+
+def sweep(args):
+    """Single-factor sweep: n in {10000, 20000, 40000}, k in {1, 16, 64},
+    FP64 and FP32 storage.  Per configuration: one untimed update/downdate
+    pair, then 3 timed pairs (HIP events around each modification on a
+    dedicated stream).  Reports ms per modification (median), updates/s,
+    effective GB/s (algorithmic bytes es n (n+1) + es n k over the median)
+    and its fraction of 8 TB/s, and the round-trip drift of L."""
+    import torch
+    import paper_1011_1173_amd as chm
+    from paper_1011_1173_amd import inputs
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream()
+    rows = []
+    for n in (10000, 20000, 40000):
+        L64 = inputs.spd_factor(n, seed=3, device="cuda")
+        for dt, es in ((torch.float64, 8), (torch.float32, 4)):
+            L0 = L64.to(dt)
+            for k in (1, 16, 64):
+                V = inputs.update_vectors(n, k, seed=3, device="cuda").to(dt)
+                L = L0.clone()
+                torch.cuda.synchronize()  # L and V were written on the default stream
+                times = []
+                with torch.cuda.stream(stream):
+                    for it in range(4):
+                        for sg in (1, -1):
+                            e0 = torch.cuda.Event(enable_timing=True)
+                            e1 = torch.cuda.Event(enable_timing=True)
+                            e0.record(stream)
+                            pend = chm.update_async(L, V, sg, stream=stream)
+                            e1.record(stream)
+                            st, _, _ = pend.status()
+                            assert st == 0, (n, k, dt, st)
+                            if it > 0:
+                                times.append(e0.elapsed_time(e1))
+                drift = float(torch.linalg.norm((L - L0).double()) / torch.linalg.norm(L0.double()))
+                med = sorted(times)[len(times) // 2]
+                byts = es * n * (n + 1) + es * n * k
+                gbs = byts / (med * 1e-3) / 1e9
+                rows.append({"n": n, "k": k, "dtype": "f64" if es == 8 else "f32s",
+                             "ms_per_modification": med, "updates_per_s": 1e3 / med,
+                             "effective_GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS,
+                             "round_trip_drift": drift})
+                print("sweep: n=%d k=%d %s %.3f ms %.0f GB/s" % (n, k, rows[-1]["dtype"], med, gbs),
+                      file=sys.stderr, flush=True)
+                del L, V
+            del L0
+        del L64
+        torch.cuda.empty_cache()
+    out = {"metric": "single-factor sweep (ms per modification, effective GB/s)",
+           "value": None, "unit": "see rows", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f64+f32s", "data": "synthetic",
+           "config": {"workload": "sweep: n in {1e4, 2e4, 4e4} x k in {1, 16, 64} x "
+                                  "{FP64, FP32 storage}, update then matching downdate"},
+           "rows": rows}
     print(json.dumps(out))
     return 0
 
@@ -311,6 +374,8 @@ def main():
         return batched(args)
     if args.mode == "served":
         return served(args)
+    if args.mode == "sweep":
+        return sweep(args)
     import torch
     import paper_1011_1173_amd as chm
     from paper_1011_1173_amd import inputs

@@ -227,6 +227,8 @@ int cholmod_server_add_factor(cholmod_server *srv, void *L, int64_t n, int64_t l
  * Queue the modification of factor `id` by V (device, (n, k) row-major, in
  * the factor's storage type; caller-owned and unchanged until the request
  * completes).  *ticket identifies the request.  Never blocks on the GPU.
+ * The server works on its own stream, which waits for no other stream: any
+ * GPU work that writes V or the factor must have completed before the call.
  */
 int cholmod_server_submit(cholmod_server *srv, int32_t id, const void *V, int64_t k, int sigma,
                           uint64_t *ticket);

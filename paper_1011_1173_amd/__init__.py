@@ -235,6 +235,8 @@ class Server:
     def add_factor(self, L: torch.Tensor) -> int:
         n, _, ldl, _ = _factor_args(L, torch.empty((L.shape[0], 0), dtype=L.dtype,
                                                    device=L.device))
+        # the server's stream does not wait for the caller's: L must be written
+        torch.cuda.current_stream(L.device).synchronize()
         fid = ctypes.c_int32(-1)
         _raise_for(_native.load().cholmod_server_add_factor(
             self._h, ctypes.c_void_p(L.data_ptr()), n, ldl,
@@ -250,6 +252,8 @@ class Server:
             V = V.view(-1, 1)
         if V.dtype != dt or V.device != L.device or not V.is_contiguous() or V.shape[0] != L.shape[0]:
             raise ArgumentError("V must be a contiguous (n, k) tensor of the factor's dtype and device")
+        # the server's stream does not wait for the caller's: V must be written
+        torch.cuda.current_stream(V.device).synchronize()
         t = ctypes.c_uint64(0)
         _raise_for(_native.load().cholmod_server_submit(
             self._h, int(fid), ctypes.c_void_p(V.data_ptr()), V.shape[1], int(sigma),
