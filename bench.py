@@ -462,6 +462,11 @@ def main():
                      "launches_per_modification": 1 + 2 * passes,
                      "avg_launch_us": avg_launch_us,
                      "alg_bytes_per_launch": bytes_per_launch},
+        # the single-factor path is bound by its serial chain of blocks, not by
+        # HBM: the time per 64-row block (and 16-column pass) is the figure to
+        # compare between versions
+        "critical_path": {"blocks_x_passes": ((n + 63) // 64) * passes,
+                          "us_per_block": mean * 1e3 / (((n + 63) // 64) * passes)},
         "round_trip_drift": drift,
         "wall_s": wall,
     }

@@ -137,7 +137,8 @@ def test_noops(orc, exact):
 
 # ----------------------------------------------------------------- failures
 @pytest.mark.parametrize("exact", [False, True])
-@pytest.mark.parametrize("n,r,k", [(40, 0, 3), (40, 17, 3), (300, 150, 16), (100, 99, 70)])
+@pytest.mark.parametrize("n,r,k", [(40, 0, 3), (40, 17, 3), (300, 150, 16), (100, 99, 70),
+                                   (200, 63, 5), (200, 64, 5), (1000, 575, 16)])
 def test_indefinite_downdate_reports_oracle_index(orc, exact, n, r, k):
     print_case("fail", n=n, r=r, k=k, exact=exact)
     L, _ = problem(n, 1, seed=33)
