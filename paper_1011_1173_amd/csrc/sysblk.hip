@@ -109,9 +109,11 @@ struct SbLds {
   union {
     double Lb[kBR][kBR + 1];  // chain: the block's original upper triangle
     double A2[kBR][kBR + 1];  // batch rest workgroups: their second apply tile
+    float A2f[kBR][kBR + 1];  // ... held in binary32 for FP32 storage
   };
   union {
     double A[kBR][kBR + 4];      // apply tile: rows of block b-1 x 64 columns
+    float Af[kBR][kBR + 4];      // ... held in binary32 for FP32 storage
     double Lh[kPad + kBR][kBR];  // helper results after the last rotation, rows -16..63
   };
   double Hb[kKP][2][kBR];   // V_j[m] after each helper rotation, by step parity
@@ -215,12 +217,23 @@ __device__ __forceinline__ void tile_issue_a(TileRegs<ST>& tr, const ST* __restr
   }
 }
 
+// The apply tiles in the storage type: the Apply to other blocks' columns
+// runs in ST, so the tile is kept in ST and no sub-step converts it.
+template <typename ST> __device__ __forceinline__ ST* tile_a(SbLds& sh);
+template <> __device__ __forceinline__ double* tile_a<double>(SbLds& sh) { return &sh.A[0][0]; }
+template <> __device__ __forceinline__ float* tile_a<float>(SbLds& sh) { return &sh.Af[0][0]; }
+template <typename ST> __device__ __forceinline__ ST* tile_a2(SbLds& sh);
+template <> __device__ __forceinline__ double* tile_a2<double>(SbLds& sh) { return &sh.A2[0][0]; }
+template <> __device__ __forceinline__ float* tile_a2<float>(SbLds& sh) { return &sh.A2f[0][0]; }
+constexpr int kLdA = kBR + 4, kLdA2 = kBR + 1;  // row strides, in elements
+
 template <typename ST>
 __device__ __forceinline__ void tile_stage(SbLds& sh, const TileRegs<ST>& tr) {
+  ST* const t = tile_a<ST>(sh);
 #pragma unroll
   for (int q = 0; q < kTilePerThread; ++q) {
     const int idx = threadIdx.x + q * kThreads;
-    sh.A[idx >> 6][idx & 63] = (double)tr.a[q];
+    t[(idx >> 6) * kLdA + (idx & 63)] = tr.a[q];
   }
 }
 
@@ -292,7 +305,7 @@ __device__ __forceinline__ void w2x2_load(ST (&w)[kOwnCols], const ST* __restric
 // with row stride LD.  Callers alternate two register sets, so that nothing
 // is copied between sub-steps.
 template <int SG, typename ST, int LD>
-__device__ __forceinline__ void sub2x2(const double* tile_in, double* tile, const RotRec* rp,
+__device__ __forceinline__ void sub2x2(const ST* tile_in, ST* tile, const RotRec* rp,
                                        int s, int h, int c0, int hf, bool first,
                                        ST (&w)[kOwnCols], ST (&xin)[2], const RotRec (&qc)[2],
                                        RotRec (&qn)[2], const ST (&fc)[2], ST (&fn)[2]) {
@@ -328,7 +341,7 @@ __device__ __forceinline__ void sub2x2(const double* tile_in, double* tile, cons
 // lt of one half of the workgroup.  No barrier inside.  The arithmetic runs
 // in the storage type ST (the records hold ST values).
 template <int SG, typename ST, int KCF, int LD>
-__device__ __forceinline__ void apply2x2(SbLds& sh, double* tile, int kc_, int lt,
+__device__ __forceinline__ void apply2x2(SbLds& sh, ST* tile, int kc_, int lt,
                                          ST (&w)[kOwnCols]) {
   const int kc = KCF ? KCF : kc_;
   const int h = (lt & 15) >> 1, c0 = own_col(lt, 0);
@@ -695,13 +708,13 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
   }
   __syncthreads();
   if (head) {
-    if (tid < kOwnThreads) apply2x2<SG, ST, KCF, kBR + 4>(sh, &sh.A[0][0], kc, tid, wa);
+    if (tid < kOwnThreads) apply2x2<SG, ST, KCF, kLdA>(sh, tile_a<ST>(sh), kc, tid, wa);
     __syncthreads();
     // the head tile's final values, and V of block b's columns for the chain
 #pragma unroll
     for (int q = 0; q < kTilePerThread; ++q) {
       const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
-      if (c < bbc) L[(pa + r) * ldl + pc + c] = (ST)sh.A[r][c];
+      if (c < bbc) L[(pa + r) * ldl + pc + c] = tile_a<ST>(sh)[r * kLdA + c];
     }
     if (tid < kOwnThreads) {
 #pragma unroll
@@ -766,24 +779,24 @@ __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_
     ST wa[kOwnCols];
     w2x2_load(wa, W, ldw, kc, j0, ncols, lt);
     records_stage(sh, rg);
-    double* const tile = half ? &sh.A2[0][0] : &sh.A[0][0];
-    const int ld = half ? kBR + 1 : kBR + 4;
+    ST* const tile = half ? tile_a2<ST>(sh) : tile_a<ST>(sh);
+    const int ld = half ? kLdA2 : kLdA;
 #pragma unroll
     for (int q = 0; q < kHalfTile; ++q) {
       const int idx = lt + q * kOwnThreads;
-      tile[(idx >> 6) * ld + (idx & 63)] = (double)ta[q];
+      tile[(idx >> 6) * ld + (idx & 63)] = ta[q];
     }
     __syncthreads();
     if (ncols > 0) {
-      if (half) apply2x2<SG, ST, KCF, kBR + 1>(sh, &sh.A2[0][0], kc, lt, wa);
-      else apply2x2<SG, ST, KCF, kBR + 4>(sh, &sh.A[0][0], kc, lt, wa);
+      if (half) apply2x2<SG, ST, KCF, kLdA2>(sh, tile_a2<ST>(sh), kc, lt, wa);
+      else apply2x2<SG, ST, KCF, kLdA>(sh, tile_a<ST>(sh), kc, lt, wa);
     }
     __syncthreads();
     if (ncols > 0) {
 #pragma unroll
       for (int q = 0; q < kHalfTile; ++q) {
         const int idx = lt + q * kOwnThreads, r = idx >> 6, c = idx & 63;
-        if (c < ncols) L[(pa + r) * ldl + j0 + c] = (ST)tile[r * ld + c];
+        if (c < ncols) L[(pa + r) * ldl + j0 + c] = tile[r * ld + c];
       }
 #pragma unroll
       for (int k = 0; k < 2; ++k)
@@ -801,20 +814,14 @@ __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_
 // j-th to start) owns the columns of block j: it applies blocks 0 .. j-1 to
 // them in row order, each as its owner publishes it, keeping V of its
 // columns in registers, then runs the chain of block j itself and publishes
-// the block's records 16 rows at a time while the chain runs.  A workgroup
+// the block's records 4 rows at a time while the chain runs.  A workgroup
 // waits only for workgroups that started before it, so every wait ends; each
 // wait is still bounded: all of a workgroup's waits end kWaitTicks after it
 // started (then the launch reports kCodeTimeout and its results are void).
 constexpr int64_t kWaitTicks = 500000000;  // steady-counter ticks (5 s at 100 MHz)
 
-// The owner's apply runs on waves 0-3, one per SIMD.  Lane (q, h, cs) =
-// 16 q + 2 h + cs of those 256 threads applies rotations 2h and 2h+1 of row
-// s - h at sub-step s to the two columns 4 q + 2 cs and 4 q + 2 cs + 1: each
-// pair of records read from LDS serves two columns, the partly rotated L_rj
-// moves to lane h+1 of its column pair with a DPP shift by two lanes (the
-// lanes of h = 0 take the next row of the tile), and the pipeline drains in
-// 7 sub-steps.
-// Wave 4 fetches the records: it waits until a prefix of the next 16 rows
+// The owner's apply runs on waves 0-3 (one per SIMD) with the two-rotation,
+// two-column lanes of sub2x2.  Wave 4 fetches the records: it waits until a prefix of the next 16 rows
 // has been published, stages those rows in sh.R and announces how far the
 // staged rows go (sh.up, by round parity); the apply waves then run the
 // sub-steps whose rows are all staged, while wave 4 fetches the next rows.
@@ -825,7 +832,7 @@ constexpr int64_t kWaitTicks = 500000000;  // steady-counter ticks (5 s at 100 M
 // block pb is the one just before the owner's own (its chain waits for this
 // apply), so wave 4 polls without delay; the owners further right poll
 // slowly, which keeps their reads of the same few records from crowding the
-// memory channels.  Same operations, in the same order, as apply_tile.
+// memory channels.  Same operations, in the same order, as apply2x2.
 template <int SG, typename ST, int KCF>
 __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
                                             ST (&w)[kOwnCols],
@@ -842,8 +849,8 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
     const int hf = (kc - 1) >> 1;          // lane holding rotation kc - 1
     const bool first = (kc & 1) != 0;      // ... as the first of its pair
     const int S = kBR + hf;                // row 63 reaches lane hf at sub-step 63 + hf
-    double* const tile = &sh.A[0][0];
-    constexpr int LD = kBR + 4;
+    ST* const tile = tile_a<ST>(sh);
+    constexpr int LD = kLdA;
     ST xin[2], fa[2], fb[2] = {(ST)0, (ST)0};  // fa, fb: only lanes h = 0 use them
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -999,7 +1006,7 @@ __global__ __launch_bounds__(kThreads) void k_sb_owner(
 #pragma unroll
     for (int q = 0; q < kTilePerThread; ++q) {
       const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
-      if (c < bbc) L[(pb + r) * ldl + pj + c] = (ST)sh.A[r][c];
+      if (c < bbc) L[(pb + r) * ldl + pj + c] = tile_a<ST>(sh)[r * kLdA + c];
     }
   }
   // V of the block's columns, after all earlier rows, starts the chain
