@@ -365,27 +365,32 @@ __device__ __forceinline__ void apply2x2(SbLds& sh, ST* tile, int kc_, int lt,
 }
 
 // ------------------------------------------------------------------ chain
-// Per-wave state lives in one register array laid out by the wave's role, so
-// that the four roles share registers.
+// A helper wave's state lives in one register array laid out by its column
+// range.
 constexpr int kSt = 13;
 
-// Wave 0 layout: st[0] radicand, st[1] 1/L_ii and st[2] L_ii from lane m-1
-// (lane 0: the row's original diagonal), st[3] V_i[m] for this step's Compute,
-// st[4], st[5] L(i-1, i+1) and L(i, i+1) rotated through columns < m,
-// st[6..8] this lane's record {c, s, 1/c} of row i-1.
-__device__ __forceinline__ void chain_init(SbLds& sh, double (&st)[kSt], int lane, int bbc) {
+// Wave 0's state, kept in separate scalars (an array would be carried
+// through the step loop as one wide register tuple and copied whole at
+// every step).
+struct ChainState {
+  double tp, il, lin;  // from lane m-1 (lane 0: the row's original diagonal):
+                       // radicand, 1/L_ii and L_ii
+  double v;            // V_i[m] for this step's Compute
+  double lo, hi;       // L(i-1, i+1) and L(i, i+1) rotated through columns < m
+  double pc, ps, pic;  // this lane's record {c, s, 1/c} of row i-1
+};
+
+__device__ __forceinline__ void chain_init(SbLds& sh, ChainState& g, int lane) {
   const DiagPre d0 = sh.dg[0];
-  st[0] = d0.t;
-  st[1] = d0.il;
-  st[2] = d0.l;
-  st[3] = sh.Hb[lane & 15][1][0];
-  st[4] = sh.fl[0].lo;
-  st[5] = sh.fl[0].hi;
-  st[6] = 1.0;
-  st[7] = 0.0;
-  st[8] = 1.0;
-#pragma unroll
-  for (int u = 9; u < kSt; ++u) st[u] = 0.0;
+  g.tp = d0.t;
+  g.il = d0.il;
+  g.lin = d0.l;
+  g.v = sh.Hb[lane & 15][1][0];
+  g.lo = sh.fl[0].lo;
+  g.hi = sh.fl[0].hi;
+  g.pc = 1.0;
+  g.ps = 0.0;
+  g.pic = 1.0;
 }
 
 // One step of wave 0.  All 64 lanes compute; lanes m >= kc carry garbage
@@ -393,7 +398,7 @@ __device__ __forceinline__ void chain_init(SbLds& sh, double (&st)[kSt], int lan
 // band row 0).  CHECK: the pipeline is filling or draining (some lane has
 // i < 0, or i + 1 >= bbc).
 template <bool CHECK, int SG>
-__device__ __forceinline__ void chain_step(SbLds& sh, double (&st)[kSt], int t, int m, int kc,
+__device__ __forceinline__ void chain_step(SbLds& sh, ChainState& g, int t, int m, int kc,
                                            int bbc) {
   const int i = t - m;
   const int jj = i + 1;
@@ -402,45 +407,43 @@ __device__ __forceinline__ void chain_step(SbLds& sh, double (&st)[kSt], int t, 
   const DiagPre dn = sh.dg[t + 1];  // t + 1 < 80
   const Fill fn = sh.fl[t + 1];
   // Compute(i, m)
-  const double tpi = st[0], ili = st[1], lin = st[2];
-  const double v = st[3];
-  const double tt = __builtin_fma(SG * v, v, tpi);
+  const double v = g.v;
+  const double tt = __builtin_fma(SG * v, v, g.tp);
   const double y = rsqrt_refined(tt);
   const double ww = tt * y;
-  const double s = v * ili;
-  const double c = ww * ili;
-  const double ic = lin * y;
+  const double s = v * g.il;
+  const double c = ww * g.il;
+  const double ic = g.lin * y;
   RotRec cur;
   cur.c = c; cur.s = s; cur.ic = ic; cur.ss = SG * s;
   const bool rec_ok = act && (!CHECK || (i >= 0 && i < bbc));
   sh.R[rec_ok ? i + kPad : kRRows - 1][m & 15] = cur;
   // rows i-1 (record of the previous step) and i applied to column jj
-  const double pc = st[6], ps = st[7], pic = st[8];
-  const double x0 = __builtin_fma(SG * ps, Wc, st[4]) * pic;
-  Wc = __builtin_fma(-ps, x0, pc * Wc);
-  const double x1 = __builtin_fma(SG * s, Wc, st[5]) * ic;
+  const double x0 = __builtin_fma(SG * g.ps, Wc, g.lo) * g.pic;
+  Wc = __builtin_fma(-g.ps, x0, g.pc * Wc);
+  const double x1 = __builtin_fma(SG * s, Wc, g.hi) * ic;
   Wc = __builtin_fma(-s, x1, c * Wc);
   Band b;
   b.lo = x0; b.hi = x1; b.d = ww; b.pad = 0.0;
   sh.Lc[act ? (CHECK ? imax(imin(i + kPad, kRRows - 1), 0) : i + kPad) : 0] = b;
   if (CHECK) {
     const bool started = i >= 0;
-    st[3] = started ? Wc : st[3];
-    st[6] = started ? c : 1.0;
-    st[7] = started ? s : 0.0;
-    st[8] = started ? ic : 1.0;
+    g.v = started ? Wc : v;
+    g.pc = started ? c : 1.0;
+    g.ps = started ? s : 0.0;
+    g.pic = started ? ic : 1.0;
   } else {
-    st[3] = Wc;
-    st[6] = c;
-    st[7] = s;
-    st[8] = ic;
+    g.v = Wc;
+    g.pc = c;
+    g.ps = s;
+    g.pic = ic;
   }
   // to lane m+1 (lane 0 takes row t+1's originals)
-  st[4] = sb_shr1(x0, fn.lo);
-  st[5] = sb_shr1(x1, fn.hi);
-  st[0] = sb_shr1(tt, dn.t);
-  st[1] = sb_shr1(y, dn.il);
-  st[2] = sb_shr1(ww, dn.l);  // L_ii after column m = t * y: what tp * il gives lane m+1
+  g.lo = sb_shr1(x0, fn.lo);
+  g.hi = sb_shr1(x1, fn.hi);
+  g.tp = sb_shr1(tt, dn.t);
+  g.il = sb_shr1(y, dn.il);
+  g.lin = sb_shr1(ww, dn.l);  // L_ii after column m = t * y: what tp * il gives lane m+1
 }
 
 // Helper wave layout (columns [MLO, MLO + CNT) of V, lane jj = block column):
@@ -494,10 +497,10 @@ __device__ __forceinline__ void helper_step(SbLds& sh, double (&st)[kSt], int t,
 // barriers, one per step (the role is wave-uniform, so no wave enters
 // another role's loop).
 template <bool CHECK, int SG>
-__device__ __forceinline__ void chain_steps(SbLds& sh, double (&st)[kSt], int t0, int t1,
+__device__ __forceinline__ void chain_steps(SbLds& sh, ChainState& g, int t0, int t1,
                                             int lane, int kc, int bbc) {
   for (int t = t0; t < t1; ++t) {
-    chain_step<CHECK, SG>(sh, st, t, lane, kc, bbc);
+    chain_step<CHECK, SG>(sh, g, t, lane, kc, bbc);
     __syncthreads();
   }
 }
@@ -574,12 +577,12 @@ __device__ __forceinline__ void chain_loops(SbLds& sh, int kc, int bbc, bool pub
   const int nsteps = bbc + kc - 1;
   const int s0 = kc - 1, s1 = imax(kc - 1, bbc - 1);
   if (wv == 0) {
-    double st[kSt];
-    chain_init(sh, st, lane, bbc);
+    ChainState g;
+    chain_init(sh, g, lane);
     __syncthreads();
-    chain_steps<true, SG>(sh, st, 0, s0, lane, kc, bbc);
-    chain_steps<false, SG>(sh, st, s0, s1, lane, kc, bbc);
-    chain_steps<true, SG>(sh, st, s1, nsteps, lane, kc, bbc);
+    chain_steps<true, SG>(sh, g, 0, s0, lane, kc, bbc);
+    chain_steps<false, SG>(sh, g, s0, s1, lane, kc, bbc);
+    chain_steps<true, SG>(sh, g, s1, nsteps, lane, kc, bbc);
   } else if (wv == 4) {
     // shares its SIMD with wave 0: passes the same barriers and publishes
     int q = 0;
