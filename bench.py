@@ -53,12 +53,13 @@ def parse():
     ap.add_argument("--n", type=int, default=5000)
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--mode", choices=["headline", "batched", "served", "sweep"],
+    ap.add_argument("--mode", choices=["headline", "batched", "served", "sweep", "ooc"],
                     default="headline",
                     help="headline: one factor, n=5000, k=16 (default); batched: 256 factors "
                          "of uneven size per call; served: a pool of factors fed by Poisson "
                          "arrivals through the served mode; sweep: single factors with n in "
-                         "{1e4, 2e4, 4e4}, k in {1, 16, 64}, FP64 and FP32 storage")
+                         "{1e4, 2e4, 4e4}, k in {1, 16, 64}, FP64 and FP32 storage; ooc: "
+                         "factors in host memory streamed in 64-row panels (n in {5e3, 2e4})")
     ap.add_argument("--batch-dtype", choices=["f64", "f32s"], default="f64",
                     help="batched mode: storage type of the factors")
     ap.add_argument("--served-seconds", type=float, default=3.0,
@@ -235,6 +236,71 @@ def sweep(args):
     return 0
 
 
+def ooc(args):
+    """Out-of-core form: the factor in host memory (pinned, and pageable for
+    n = 5000), V on the GPU, k = 16, FP64.  Per configuration one untimed
+    update/downdate pair, then 2 timed pairs (wall clock: the call is
+    synchronous).  Reports ms per modification, the host<->device bytes
+    moved (every 64-row panel of the upper triangle copied in and out once
+    per 16-column pass), their rate, the device bytes used, and the device
+    (in-core) time of the same modification for comparison."""
+    import torch
+    import paper_1011_1173_amd as chm
+    from paper_1011_1173_amd import inputs
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    k, es = 16, 8
+    rows = []
+    for n, pinned in ((5000, True), (5000, False), (20000, True)):
+        Ld = inputs.spd_factor(n, seed=4, device="cuda")
+        V = inputs.update_vectors(n, k, seed=4, device="cuda")
+        # device time of the same modification
+        t_dev = []
+        for sg in (1, -1, 1, -1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            chm.update(Ld, V, sg)
+            torch.cuda.synchronize()
+            t_dev.append(time.perf_counter() - t0)
+        L0 = Ld.cpu()
+        L = L0.pin_memory() if pinned else L0.clone()
+        del Ld
+        torch.cuda.empty_cache()
+        ws = torch.empty(chm.workspace_bytes_ooc(n, k), dtype=torch.uint8, device=dev)
+        times = []
+        for it in range(3):
+            for sg in (1, -1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                chm.update_ooc(L, V, sg, workspace=ws)
+                dt = time.perf_counter() - t0
+                if it > 0:
+                    times.append(dt)
+        drift = float(torch.linalg.norm(L - L0) / torch.linalg.norm(L0))
+        med = sorted(times)[len(times) // 2]
+        moved = sum(2 * min(64, n - r0) * (n - r0) * es for r0 in range(0, n, 64))
+        rows.append({"n": n, "k": k, "host_memory": "pinned" if pinned else "pageable",
+                     "ms_per_modification": med * 1e3, "updates_per_s": 1.0 / med,
+                     "host_device_bytes": moved, "host_device_GBps": moved / med / 1e9,
+                     "device_bytes": ws.numel(), "dense_factor_bytes": n * n * es,
+                     "incore_ms_per_modification": sorted(t_dev[2:])[0] * 1e3,
+                     "round_trip_drift": drift})
+        print("ooc: n=%d %s %.2f ms (%.1f GB/s host<->device; in-core %.2f ms)" % (
+            n, rows[-1]["host_memory"], med * 1e3, moved / med / 1e9,
+            rows[-1]["incore_ms_per_modification"]), file=sys.stderr, flush=True)
+        del L, L0, V, ws
+        torch.cuda.empty_cache()
+    out = {"metric": "out-of-core modification (factor in host memory)",
+           "value": rows[-1]["ms_per_modification"], "unit": "ms per modification (n=20000)",
+           "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "out-of-core: n in {5000, 20000}, k = 16, FP64, factor in "
+                                  "host memory, update then matching downdate"},
+           "rows": rows}
+    print(json.dumps(out))
+    return 0
+
+
 def served(args):
     """Served workload: a pool of factors with sizes cycled over {1024, 2048,
     4096, 8192, 16384}, each with 4 prior V's already added (untimed).  A
@@ -376,6 +442,8 @@ def main():
         return served(args)
     if args.mode == "sweep":
         return sweep(args)
+    if args.mode == "ooc":
+        return ooc(args)
     import torch
     import paper_1011_1173_amd as chm
     from paper_1011_1173_amd import inputs

@@ -194,6 +194,34 @@ int cholmod_update_batched(const cholmod_desc *descs, int64_t count, void *ws, s
                            int64_t *d_info, cholmod_stream_t stream);
 
 /*
+ * Out-of-core modification of a factor held in HOST memory (the paper keeps
+ * only O(n) of L on the GPU, Section 4; here for factors larger than HBM).
+ * L is streamed through the device in row panels of 64 rows: panel b
+ * (rows 64b .. 64b+63, columns 64b .. n-1) is copied in before the block
+ * step that factors block b and copied back after the next step has applied
+ * block b to the columns right of block b+1.  The arithmetic is that of the
+ * batched schedule, so the result is bit for bit the one the device entry
+ * point of the same storage type gives.  Synchronous: returns when L in
+ * host memory holds the result.
+ *   L_host  HOST double* (CHOLMOD_F64) or float* (CHOLMOD_F32S), (n, ldl)
+ *           row-major upper triangle, modified in place; pinned memory
+ *           (hipHostMalloc) copies fastest, pageable memory works
+ *   V       DEVICE, (n, k) row-major in the storage type, unchanged
+ *   ws      device workspace of at least cholmod_workspace_bytes_ooc(n, k,
+ *           dtype) bytes, 256-byte aligned; NULL: the call allocates and
+ *           frees it.  Device memory used: 3 panels of 64 x n elements plus
+ *           V's copy and the rotation records, O(n (64 + k)).
+ *   info    HOST int64* (may be NULL): the raw info word
+ * Returns CHOLMOD_OK, CHOLMOD_ERR_NOT_PD / CHOLMOD_ERR_BAD_DIAG (L's rows at
+ * and after the failing row are unspecified), CHOLMOD_ERR_ARG before any
+ * HIP call for bad arguments, or CHOLMOD_ERR_HIP.
+ */
+size_t cholmod_workspace_bytes_ooc(int64_t n, int64_t k, int dtype);
+int cholmod_update_ooc(void *L_host, const void *V, int64_t n, int64_t k, int64_t ldl,
+                       int sigma, int dtype, void *ws, size_t ws_bytes, int64_t *info,
+                       cholmod_stream_t stream);
+
+/*
  * Served mode: factors registered once, then a stream of requests (one
  * update or downdate of one factor by a caller-owned V) batched
  * continuously onto one GPU by a library worker thread.  Requests of one

@@ -19,7 +19,7 @@ from ._native import (ERR_ARG, ERR_BAD_DIAG, ERR_HIP, ERR_NOT_PD, F32S, F64, FLA
                       FLAG_EXACT, INFO_NONE, OK, LibraryMissing)
 
 __all__ = ["update", "update_async", "update_batched", "update_batched_async",
-           "workspace_bytes", "CholmodError", "ArgumentError", "NotPositiveDefinite",
+           "update_ooc", "workspace_bytes", "workspace_bytes_ooc", "CholmodError", "ArgumentError", "NotPositiveDefinite",
            "BadDiagonal", "HipError", "LibraryMissing", "Pending", "PendingBatch", "Server"]
 
 
@@ -156,6 +156,50 @@ def update(L: torch.Tensor, V: torch.Tensor, sigma: int, *, exact: bool = False,
     column), or ArgumentError for bad shapes and types.
     """
     update_async(L, V, sigma, exact=exact, blocked=blocked, stream=stream).wait()
+
+
+def workspace_bytes_ooc(n: int, k: int, dtype: int = F64) -> int:
+    """Device workspace bytes of update_ooc for an n x k problem (O(n (64 + k)))."""
+    return int(_native.load().cholmod_workspace_bytes_ooc(n, k, dtype))
+
+
+def update_ooc(L: torch.Tensor, V: torch.Tensor, sigma: int, *, stream=None,
+               workspace: torch.Tensor | None = None) -> None:
+    """Out-of-core form (cholmod_update_ooc): L is a HOST tensor (float64, or
+    float32 for FP32 storage; pinned memory copies fastest) streamed through
+    the GPU in 64-row panels; V is on the GPU.  Synchronous; raises like
+    ``update``."""
+    if not isinstance(L, torch.Tensor) or not isinstance(V, torch.Tensor):
+        raise ArgumentError("L and V must be torch tensors")
+    if L.device.type != "cpu":
+        raise ArgumentError("L must be a host (CPU) tensor")
+    if L.dtype not in (torch.float64, torch.float32) or V.dtype != L.dtype:
+        raise ArgumentError("L and V must both be float64, or both float32 (FP32 storage)")
+    if V.device.type != "cuda":
+        raise ArgumentError("V must be on the GPU")
+    if L.dim() != 2 or L.stride(1) != 1 or L.shape[1] < L.shape[0]:
+        raise ArgumentError("L must be (n, >= n) with unit column stride")
+    n = L.shape[0]
+    ldl = L.stride(0) if n > 1 else max(1, L.shape[1])
+    if V.dim() == 1:
+        V = V.view(-1, 1)
+    if V.dim() != 2 or V.shape[0] != n or not V.is_contiguous():
+        raise ArgumentError("V must be a contiguous (n, k) tensor")
+    k = V.shape[1]
+    dtype = F32S if L.dtype == torch.float32 else F64
+    stream = torch.cuda.current_stream(V.device) if stream is None else stream
+    lib = _native.load()
+    ws_ptr, ws_len = None, 0
+    if workspace is not None:
+        ws_ptr, ws_len = ctypes.c_void_p(workspace.data_ptr()), workspace.numel()
+    info = ctypes.c_int64(INFO_NONE)
+    st = lib.cholmod_update_ooc(ctypes.c_void_p(L.data_ptr()), ctypes.c_void_p(V.data_ptr()),
+                                n, k, ldl, int(sigma), dtype, ws_ptr, ws_len,
+                                ctypes.byref(info), _stream_handle(stream))
+    if st in (ERR_NOT_PD, ERR_BAD_DIAG):
+        _, row, col = _native.decode_info(int(info.value), k)
+        _raise_for(st, row, col)
+    _raise_for(st)
 
 
 class PendingBatch:

@@ -22,6 +22,7 @@ EXPORTS = (
     "cholmod_workspace_bytes", "cholmod_update", "cholmod_update_async",
     "cholmod_update_ex", "cholmod_update_f32s", "cholmod_update_f32s_async",
     "cholmod_workspace_bytes_batched", "cholmod_update_batched",
+    "cholmod_workspace_bytes_ooc", "cholmod_update_ooc",
     "cholmod_server_create", "cholmod_server_add_factor", "cholmod_server_submit",
     "cholmod_server_poll", "cholmod_server_drain", "cholmod_server_destroy",
 )
@@ -74,6 +75,11 @@ def load():
     lib.cholmod_update_f32s.restype = ci
     lib.cholmod_update_f32s_async.argtypes = [p, p, i64, i64, i64, ci, p, sz, p, p]
     lib.cholmod_update_f32s_async.restype = ci
+    lib.cholmod_workspace_bytes_ooc.argtypes = [i64, i64, ci]
+    lib.cholmod_workspace_bytes_ooc.restype = sz
+    lib.cholmod_update_ooc.argtypes = [p, p, i64, i64, i64, ci, ci, p, sz,
+                                       ctypes.POINTER(i64), p]
+    lib.cholmod_update_ooc.restype = ci
     dp = ctypes.POINTER(Desc)
     lib.cholmod_workspace_bytes_batched.argtypes = [dp, i64]
     lib.cholmod_workspace_bytes_batched.restype = sz

@@ -24,6 +24,9 @@ hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, floa
                           double sg, void* T, int64_t* info, int64_t* stop, int32_t* flags);
 hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
                             const BatchEntry* d_ent, const BatchStep* steps, int64_t nsteps);
+hipError_t run_sysblk_batch_prepare(hipStream_t st, const BatchFactor* d_fac, int64_t count);
+hipError_t run_sysblk_batch_step(hipStream_t st, const BatchFactor* d_fac,
+                                 const BatchEntry* d_ent, const BatchStep& S);
 
 namespace {
 
@@ -288,6 +291,8 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P)
       const cholmod_desc& d = descs[f];
       const int64_t pass = s / blocks[f], b = s % blocks[f];
       BatchEntry e;
+      e.Lc = d.L;
+      e.La = d.L;
       e.pc = b * kBlock;
       e.pa = b > 0 ? e.pc - kBlock : -1;
       e.m0 = pass * kPass;
@@ -342,6 +347,142 @@ int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_
   hipError_t e = run_sysblk_batch(st, d_fac, count, d_ent, P.steps.data(),
                                   (int64_t)P.steps.size());
   return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
+}
+
+// ------------------------------------------------------------ out-of-core
+// A factor in host memory streamed through the device in row panels of 64
+// rows (block b's rows, columns b*64 .. n-1).  The factor runs the batched
+// schedule (one launch per block step); step b touches only the rows of
+// blocks b and b-1, so panel b is uploaded before step b and downloaded
+// after step b+1 (or after step b for the last block of a pass).  Panel p
+// lives in slot p mod 3, so the upload of panel b never overwrites a panel
+// still in use; a slot holds 64 rows of n elements (row pitch n) and keeps
+// the column index of the factor.
+//   workspace = [batch workspace of the factor (row pitch n)] [info word]
+//               [3 slots of 64 x n elements]
+struct OocLayout {
+  size_t batch = 0, info = 0, slots = 0, slot_bytes = 0, total = 0;
+};
+
+// A descriptor for planning only: the planner checks that the pointers are
+// set but never dereferences them.
+cholmod_desc ooc_desc(void* L_host, const void* V, int64_t n, int64_t k, int sigma, int dtype) {
+  cholmod_desc d;
+  d.L = L_host;
+  d.V = V;
+  d.n = n;
+  d.k = k;
+  d.ldl = n > 1 ? n : 1;  // row pitch of a device slot
+  d.sigma = sigma;
+  d.dtype = dtype;
+  return d;
+}
+
+bool ooc_layout(int64_t n, int64_t k, int dtype, OocLayout* out) {
+  if (n < 0 || k < 0 || (dtype != CHOLMOD_F64 && dtype != CHOLMOD_F32S)) return false;
+  // non-null placeholders: sizing does not look at the pointers
+  const cholmod_desc d = ooc_desc((void*)kAlign, (const void*)kAlign, n, k, 1, dtype);
+  const size_t batch = batch_workspace_bytes(&d, 1);
+  if (batch == 0) return false;
+  const size_t es = dtype == CHOLMOD_F64 ? 8 : 4;
+  if (!mul_ok(kBlock * (int64_t)es, n > 1 ? n : 1, INT64_MAX / 8)) return false;
+  OocLayout L;
+  L.batch = batch;
+  L.info = align_up(batch);
+  L.slots = L.info + kAlign;
+  L.slot_bytes = align_up((size_t)(kBlock * (n > 1 ? n : 1)) * es);
+  L.total = L.slots + 3 * L.slot_bytes;
+  *out = L;
+  return true;
+}
+
+int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, int sigma,
+               int dtype, void* ws, size_t ws_bytes, hipStream_t st, int64_t* info_out) {
+  if (info_out) *info_out = CHOLMOD_INFO_NONE;
+  if (dtype != CHOLMOD_F64 && dtype != CHOLMOD_F32S) return CHOLMOD_ERR_ARG;
+  int v = validate(L_host, V, n, k, ldl, sigma);
+  if (v) return v;
+  OocLayout lay;
+  if (!ooc_layout(n, k, dtype, &lay)) return CHOLMOD_ERR_ARG;
+  if (ws != nullptr && (ws_bytes < lay.total || ((uintptr_t)ws % kAlign) != 0))
+    return CHOLMOD_ERR_ARG;
+  if (n == 0 || k == 0) return CHOLMOD_OK;
+  const cholmod_desc d = ooc_desc(L_host, V, n, k, sigma, dtype);
+  bool own = false;
+  if (ws == nullptr) {
+    if (hipMalloc(&ws, lay.total) != hipSuccess) return CHOLMOD_ERR_HIP;
+    own = true;
+  }
+  int rc = CHOLMOD_OK;
+  int64_t host_info = CHOLMOD_INFO_NONE;
+  do {
+    BatchPlan P;
+    rc = plan_batch(&d, 1, (char*)ws, &P);
+    if (rc) break;
+    char* base = (char*)ws;
+    int64_t* d_info = (int64_t*)(base + lay.info);
+    const uintptr_t slots = (uintptr_t)(base + lay.slots);
+    const int64_t es = dtype == CHOLMOD_F64 ? 8 : 4;
+    // device address of element (b * 64, 0) of a panel: slot base minus the
+    // rows before the block, so the kernels index rows and columns as in L
+    auto row_base = [&](int64_t b) -> void* {
+      const uintptr_t slot = slots + (uintptr_t)(b % 3) * lay.slot_bytes;
+      return (void*)(slot - (uintptr_t)(b * kBlock * n * es));
+    };
+    P.fac[0].L = nullptr;  // the entries carry the panel addresses
+    P.fac[0].info = d_info;
+    for (BatchEntry& e : P.ent) {
+      const int64_t b = e.pc / kBlock;
+      e.Lc = row_base(b);
+      e.La = e.pa >= 0 ? row_base(b - 1) : e.Lc;
+    }
+    std::vector<char> tables(P.table_bytes);
+    std::memcpy(tables.data(), P.fac.data(), sizeof(BatchFactor));
+    std::memcpy(tables.data() + P.off_ent, P.ent.data(), P.ent.size() * sizeof(BatchEntry));
+    if (hipMemcpyAsync(ws, tables.data(), P.table_bytes, hipMemcpyHostToDevice, st) !=
+        hipSuccess) {
+      rc = CHOLMOD_ERR_HIP;
+      break;
+    }
+    const BatchFactor* d_fac = (const BatchFactor*)ws;
+    const BatchEntry* d_ent = (const BatchEntry*)(base + P.off_ent);
+    if (run_sysblk_batch_prepare(st, d_fac, 1) != hipSuccess) {
+      rc = CHOLMOD_ERR_HIP;
+      break;
+    }
+    const int64_t nb = ceil_div(n, kBlock);
+    // rows [b*64, b*64 + rows) of L, columns b*64 .. n-1, to or from its slot
+    auto panel = [&](int64_t b, bool up) {
+      const int64_t r0 = b * kBlock, rows = std::min(kBlock, n - r0);
+      char* dev = (char*)row_base(b) + (r0 * n + r0) * es;
+      char* host = (char*)L_host + (r0 * ldl + r0) * es;
+      const size_t width = (size_t)((n - r0) * es);
+      return up ? hipMemcpy2DAsync(dev, (size_t)(n * es), host, (size_t)(ldl * es), width,
+                                   (size_t)rows, hipMemcpyHostToDevice, st)
+                : hipMemcpy2DAsync(host, (size_t)(ldl * es), dev, (size_t)(n * es), width,
+                                   (size_t)rows, hipMemcpyDeviceToHost, st);
+    };
+    for (int64_t s = 0; s < (int64_t)P.steps.size() && rc == CHOLMOD_OK; ++s) {
+      const int64_t b = s % nb;
+      hipError_t e = panel(b, true);
+      if (e == hipSuccess) e = run_sysblk_batch_step(st, d_fac, d_ent, P.steps[s]);
+      if (e == hipSuccess && b > 0) e = panel(b - 1, false);
+      if (e == hipSuccess && b == nb - 1) e = panel(b, false);
+      if (e != hipSuccess) rc = CHOLMOD_ERR_HIP;
+    }
+    if (rc) break;
+    if (hipMemcpyAsync(&host_info, d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      rc = CHOLMOD_ERR_HIP;
+  } while (false);
+  if (own) {
+    if (hipStreamSynchronize(st) != hipSuccess) rc = CHOLMOD_ERR_HIP;
+    hipFree(ws);
+  }
+  if (rc) return rc;
+  if (info_out) *info_out = host_info;
+  return cholmod_decode_info(host_info, k, nullptr, nullptr);
 }
 
 }  // namespace chm
@@ -419,6 +560,19 @@ int cholmod_update_f32s(float* L, const float* V, int64_t n, int64_t k, int64_t 
                   [&](void* ws, size_t bytes, int64_t* d_info, hipStream_t st) {
                     return enqueue_f32s(L, V, n, k, ldl, sigma, ws, bytes, d_info, st);
                   });
+}
+
+size_t cholmod_workspace_bytes_ooc(int64_t n, int64_t k, int dtype) {
+  OocLayout lay;
+  if (!ooc_layout(n, k, dtype, &lay)) return 0;
+  return lay.total;
+}
+
+int cholmod_update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl,
+                       int sigma, int dtype, void* ws, size_t ws_bytes, int64_t* info,
+                       cholmod_stream_t stream) {
+  return update_ooc(L_host, V, n, k, ldl, sigma, dtype, ws, ws_bytes, (hipStream_t)stream,
+                    info);
 }
 
 size_t cholmod_workspace_bytes_batched(const cholmod_desc* descs, int64_t count) {

@@ -20,8 +20,14 @@ struct BatchFactor {
 };
 
 // One factor's share of one step: block [pc, pc + bbc) of pass m0 (device
-// table; a step's entries are contiguous, longest factor first).
+// table; a step's entries are contiguous, longest factor first).  Lc and La
+// address the rows of block pc and of block pa: element (i, j) of L is at
+// Lc + i * ldl + j for i in block pc and at La + i * ldl + j for i in block
+// pa (both are the factor's L, except for a factor streamed in row panels,
+// whose blocks sit in separate device buffers).
 struct BatchEntry {
+  void* Lc;
+  void* La;
   int64_t pc, pa, m0;
   int32_t f;       // factor index
   int32_t bbc;     // rows of the block

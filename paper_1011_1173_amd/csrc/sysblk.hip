@@ -657,7 +657,8 @@ __device__ __forceinline__ void chain_finish(SbLds& sh, ST* __restrict__ L, int6
 // workgroup applies block b-1 to two of the 64-column tiles right of block
 // b, one per half of its waves.
 template <int SG, typename ST, int KCF>
-__device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t ldl,
+__device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, ST* __restrict__ La,
+                                         int64_t ldl,
                                          ST* __restrict__ W, int64_t ldw, int kc_,
                                          int64_t kfull, int64_t m0, int64_t pc, int bbc,
                                          int64_t pa, GRec<ST>* __restrict__ T,
@@ -674,7 +675,7 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
   TileRegs<ST> tr;
   ST wa[kOwnCols];
   if (head) {
-    tile_issue_a(tr, L, ldl, pa, pc, bbc);
+    tile_issue_a(tr, La, ldl, pa, pc, bbc);
     if (tid < kOwnThreads) w2x2_load(wa, W, ldw, kc, pc, bbc, tid);
   }
   constexpr int kHbPerThread = kBR * kKP / kThreads;  // 2
@@ -717,7 +718,7 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
 #pragma unroll
     for (int q = 0; q < kTilePerThread; ++q) {
       const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
-      if (c < bbc) L[(pa + r) * ldl + pc + c] = tile_a<ST>(sh)[r * kLdA + c];
+      if (c < bbc) La[(pa + r) * ldl + pc + c] = tile_a<ST>(sh)[r * kLdA + c];
     }
     if (tid < kOwnThreads) {
 #pragma unroll
@@ -751,7 +752,8 @@ __device__ __forceinline__ void chain_wg(SbLds& sh, ST* __restrict__ L, int64_t 
 // 2 (wg - 1) and 2 (wg - 1) + 1 right of block b (waves 0-3 the first, in
 // sh.A, waves 4-7 the second, in sh.A2).
 template <int SG, typename ST, int KCF>
-__device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_t ldl,
+__device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, ST* __restrict__ La,
+                                           int64_t ldl,
                                            ST* __restrict__ W, int64_t ldw, int kc,
                                            int64_t kfull, int64_t m0, int64_t n, int64_t pc,
                                            int bbc, int64_t pa, GRec<ST>* __restrict__ T,
@@ -763,7 +765,7 @@ __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_
   __syncthreads();
   const int64_t lim = sh.lim;
   if (wg == 0) {
-    chain_wg<SG, ST, KCF>(sh, L, ldl, W, ldw, kc, kfull, m0, pc, bbc, pa, T, info, stop_row,
+    chain_wg<SG, ST, KCF>(sh, L, La, ldl, W, ldw, kc, kfull, m0, pc, bbc, pa, T, info, stop_row,
                           lim);
   } else {
     if (pa < 0 || pa >= lim) return;
@@ -777,7 +779,7 @@ __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_
 #pragma unroll
     for (int q = 0; q < kHalfTile; ++q) {
       const int idx = lt + q * kOwnThreads, r = idx >> 6, c = idx & 63;
-      ta[q] = c < ncols ? L[(pa + r) * ldl + j0 + c] : (ST)0;
+      ta[q] = c < ncols ? La[(pa + r) * ldl + j0 + c] : (ST)0;
     }
     ST wa[kOwnCols];
     w2x2_load(wa, W, ldw, kc, j0, ncols, lt);
@@ -799,7 +801,7 @@ __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, int64_
 #pragma unroll
       for (int q = 0; q < kHalfTile; ++q) {
         const int idx = lt + q * kOwnThreads, r = idx >> 6, c = idx & 63;
-        if (c < ncols) L[(pa + r) * ldl + j0 + c] = tile[r * ld + c];
+        if (c < ncols) La[(pa + r) * ldl + j0 + c] = tile[r * ld + c];
       }
 #pragma unroll
       for (int k = 0; k < 2; ++k)
@@ -1064,24 +1066,30 @@ __global__ __launch_bounds__(kThreads) void k_sb_batch(const BatchFactor* __rest
   const BatchEntry E = ent[e];
   const BatchFactor F = fac[E.f];
   if (F.dtype == kStoreF64) {
-    double* L = (double*)F.L;
+    double* L = (double*)E.Lc;
+    double* La = (double*)E.La;
     double* W = (double*)F.W + E.m0;
     GRec<double>* T = (GRec<double>*)F.T;
     if (F.sigma > 0)
-      block_work<1, double, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+      block_work<1, double, 0>(sh, L, La, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc,
+                               E.pa, T,
                                F.info, F.stop, wg);
     else
-      block_work<-1, double, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+      block_work<-1, double, 0>(sh, L, La, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc,
+                                E.pa, T,
                                 F.info, F.stop, wg);
   } else {
-    float* L = (float*)F.L;
+    float* L = (float*)E.Lc;
+    float* La = (float*)E.La;
     float* W = (float*)F.W + E.m0;
     GRec<float>* T = (GRec<float>*)F.T;
     if (F.sigma > 0)
-      block_work<1, float, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+      block_work<1, float, 0>(sh, L, La, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc,
+                              E.pa, T,
                               F.info, F.stop, wg);
     else
-      block_work<-1, float, 0>(sh, L, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc, E.pa, T,
+      block_work<-1, float, 0>(sh, L, La, F.ldl, W, F.k, E.kc, F.k, E.m0, F.n, E.pc, E.bbc,
+                               E.pa, T,
                                F.info, F.stop, wg);
   }
 }
@@ -1127,19 +1135,28 @@ hipError_t run_sysblk_t(hipStream_t st, ST* L, int64_t n, int64_t ldl, ST* W, in
 }  // namespace
 
 // Batched launches: one preparation launch, then one launch per step.
-hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
-                            const BatchEntry* d_ent, const BatchStep* steps, int64_t nsteps) {
+hipError_t run_sysblk_batch_prepare(hipStream_t st, const BatchFactor* d_fac, int64_t count) {
   if (count > 0) {
     const unsigned fy = (unsigned)count;
     hipLaunchKernelGGL(k_prepare_batch, dim3(8, fy), dim3(256), 0, st, d_fac);
   }
-  for (int64_t s = 0; s < nsteps; ++s) {
-    const BatchStep& S = steps[s];
-    if (S.nent == 0) continue;
+  return hipGetLastError();
+}
+
+hipError_t run_sysblk_batch_step(hipStream_t st, const BatchFactor* d_fac,
+                                 const BatchEntry* d_ent, const BatchStep& S) {
+  if (S.nent > 0)
     hipLaunchKernelGGL(k_sb_batch, dim3((unsigned)(S.nent + S.nrest)), dim3(kThreads), 0, st,
                        d_fac, d_ent + S.off, (int)S.nent);
-  }
   return hipGetLastError();
+}
+
+hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
+                            const BatchEntry* d_ent, const BatchStep* steps, int64_t nsteps) {
+  hipError_t e = run_sysblk_batch_prepare(st, d_fac, count);
+  for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s)
+    e = run_sysblk_batch_step(st, d_fac, d_ent, steps[s]);
+  return e;
 }
 
 // Fast blocked schedule: V columns in passes of 16, one owner launch per

@@ -151,3 +151,52 @@ def test_python_binding_rejects_bad_tensors():
         chm.update(L, V, 1)  # CPU tensors are not accepted
     with pytest.raises(chm.ArgumentError):
         chm.update(L.float(), V.float(), 1)
+
+
+def test_ooc_workspace_is_linear_in_n(nat):
+    lib = nat.load()
+    ws = lib.cholmod_workspace_bytes_ooc
+    assert ws(-1, 4, nat.F64) == 0
+    assert ws(10, -1, nat.F64) == 0
+    assert ws(10, 4, 9) == 0
+    a, b = ws(10_000, 16, nat.F64), ws(20_000, 16, nat.F64)
+    assert 0 < a < b
+    # O(n (64 + k)) device bytes: doubling n at most doubles it (plus alignment)
+    assert b <= 2 * a + 4096
+    # three 64-row panels of n elements dominate: at least 3 * 64 * n * 8 bytes
+    assert a >= 3 * 64 * 10_000 * 8
+    assert ws(10_000, 16, nat.F32S) < a
+
+
+def test_ooc_bad_arguments_rejected_on_host(nat):
+    lib = nat.load()
+    p = ctypes.c_void_p
+    host = (ctypes.c_double * 16)()
+    info = ctypes.c_int64(0)
+    dev = p(256)  # never dereferenced: the calls fail in validation
+    call = lambda L, V, n, k, ldl, sg, dt, ws=None, wsb=0: lib.cholmod_update_ooc(
+        L, V, n, k, ldl, sg, dt, ws, wsb, ctypes.byref(info), None)
+    L = ctypes.cast(host, p)
+    assert call(None, dev, 4, 2, 4, 1, nat.F64) == nat.ERR_ARG      # no L
+    assert call(L, None, 4, 2, 4, 1, nat.F64) == nat.ERR_ARG        # no V
+    assert call(L, dev, 4, 2, 3, 1, nat.F64) == nat.ERR_ARG         # ldl < n
+    assert call(L, dev, 4, 2, 4, 0, nat.F64) == nat.ERR_ARG         # sigma
+    assert call(L, dev, 4, 2, 4, 1, 5) == nat.ERR_ARG               # dtype
+    assert call(L, dev, -1, 2, 4, 1, nat.F64) == nat.ERR_ARG        # n < 0
+    assert call(L, dev, 4, 2, 4, 1, nat.F64, p(256), 16) == nat.ERR_ARG   # small workspace
+    big = lib.cholmod_workspace_bytes_ooc(4, 2, nat.F64)
+    assert call(L, dev, 4, 2, 4, 1, nat.F64, p(257), big) == nat.ERR_ARG  # misaligned
+    # nothing to do: no HIP call, L untouched
+    assert call(L, dev, 0, 2, 1, 1, nat.F64) == nat.OK
+    assert call(L, dev, 4, 0, 4, 1, nat.F64) == nat.OK
+    assert info.value == nat.INFO_NONE
+
+
+def test_ooc_python_binding_rejects_bad_tensors():
+    import torch
+    import paper_1011_1173_amd as chm
+    L = torch.eye(4, dtype=torch.float64)
+    with pytest.raises(chm.ArgumentError):
+        chm.update_ooc(L, torch.zeros(4, 2, dtype=torch.float64), 1)   # V on the host
+    with pytest.raises(chm.ArgumentError):
+        chm.update_ooc(L.float(), torch.zeros(4, 2, dtype=torch.float64), 1)
