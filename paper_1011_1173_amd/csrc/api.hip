@@ -451,25 +451,65 @@ int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, i
       break;
     }
     const int64_t nb = ceil_div(n, kBlock);
+    // Copies in run on `up`, copies out on `down`, steps on `st`: the copy
+    // engines move a panel in and another out while a step runs.  Events:
+    // in_done[slot] (panel copied in), out_done[slot] (panel copied out),
+    // step_done.  A panel is copied into a slot after the slot's previous
+    // panel has been copied out, and (in a later pass) after its own copy
+    // out of the previous pass: both are ordered on `down` before the
+    // latest out_done record of the slot.
+    hipStream_t up = nullptr, down = nullptr;
+    hipEvent_t in_done[3] = {}, out_done[3] = {}, step_done = nullptr;
+    auto create = [&]() {
+      if (hipStreamCreateWithFlags(&up, hipStreamNonBlocking) != hipSuccess) return false;
+      if (hipStreamCreateWithFlags(&down, hipStreamNonBlocking) != hipSuccess) return false;
+      for (int q = 0; q < 3; ++q) {
+        if (hipEventCreateWithFlags(&in_done[q], hipEventDisableTiming) != hipSuccess) return false;
+        if (hipEventCreateWithFlags(&out_done[q], hipEventDisableTiming) != hipSuccess)
+          return false;
+      }
+      return hipEventCreateWithFlags(&step_done, hipEventDisableTiming) == hipSuccess;
+    };
     // rows [b*64, b*64 + rows) of L, columns b*64 .. n-1, to or from its slot
-    auto panel = [&](int64_t b, bool up) {
+    auto panel = [&](int64_t b, bool in, hipStream_t cs) {
       const int64_t r0 = b * kBlock, rows = std::min(kBlock, n - r0);
       char* dev = (char*)row_base(b) + (r0 * n + r0) * es;
       char* host = (char*)L_host + (r0 * ldl + r0) * es;
       const size_t width = (size_t)((n - r0) * es);
-      return up ? hipMemcpy2DAsync(dev, (size_t)(n * es), host, (size_t)(ldl * es), width,
-                                   (size_t)rows, hipMemcpyHostToDevice, st)
+      return in ? hipMemcpy2DAsync(dev, (size_t)(n * es), host, (size_t)(ldl * es), width,
+                                   (size_t)rows, hipMemcpyHostToDevice, cs)
                 : hipMemcpy2DAsync(host, (size_t)(ldl * es), dev, (size_t)(n * es), width,
-                                   (size_t)rows, hipMemcpyDeviceToHost, st);
+                                   (size_t)rows, hipMemcpyDeviceToHost, cs);
     };
-    for (int64_t s = 0; s < (int64_t)P.steps.size() && rc == CHOLMOD_OK; ++s) {
-      const int64_t b = s % nb;
-      hipError_t e = panel(b, true);
-      if (e == hipSuccess) e = run_sysblk_batch_step(st, d_fac, d_ent, P.steps[s]);
-      if (e == hipSuccess && b > 0) e = panel(b - 1, false);
-      if (e == hipSuccess && b == nb - 1) e = panel(b, false);
-      if (e != hipSuccess) rc = CHOLMOD_ERR_HIP;
+    auto copy_out = [&](int64_t b) {
+      if (hipStreamWaitEvent(down, step_done, 0) != hipSuccess) return false;
+      if (panel(b, false, down) != hipSuccess) return false;
+      return hipEventRecord(out_done[b % 3], down) == hipSuccess;
+    };
+    bool good = create();
+    for (int64_t s = 0; good && s < (int64_t)P.steps.size(); ++s) {
+      const int64_t b = s % nb, q = b % 3;
+      good = hipStreamWaitEvent(up, out_done[q], 0) == hipSuccess &&
+             panel(b, true, up) == hipSuccess && hipEventRecord(in_done[q], up) == hipSuccess &&
+             hipStreamWaitEvent(st, in_done[q], 0) == hipSuccess &&
+             run_sysblk_batch_step(st, d_fac, d_ent, P.steps[s]) == hipSuccess &&
+             hipEventRecord(step_done, st) == hipSuccess;
+      if (good && b > 0) good = copy_out(b - 1);
+      if (good && b == nb - 1) good = copy_out(b);
     }
+    // the caller's stream waits for the last copies out
+    if (good && nb > 0) good = hipStreamWaitEvent(st, out_done[(nb - 1) % 3], 0) == hipSuccess;
+    if (good && nb > 1) good = hipStreamWaitEvent(st, out_done[(nb - 2) % 3], 0) == hipSuccess;
+    if (up && hipStreamSynchronize(up) != hipSuccess) good = false;
+    if (down && hipStreamSynchronize(down) != hipSuccess) good = false;
+    for (int q = 0; q < 3; ++q) {
+      if (in_done[q]) hipEventDestroy(in_done[q]);
+      if (out_done[q]) hipEventDestroy(out_done[q]);
+    }
+    if (step_done) hipEventDestroy(step_done);
+    if (up) hipStreamDestroy(up);
+    if (down) hipStreamDestroy(down);
+    if (!good) rc = CHOLMOD_ERR_HIP;
     if (rc) break;
     if (hipMemcpyAsync(&host_info, d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st) !=
             hipSuccess ||
