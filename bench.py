@@ -100,7 +100,9 @@ def batched(args):
     (seeded), each with 2 V's already added (untimed).  One timed batch gives
     every factor either an update by a new V or the downdate of a V still in
     its added set (50/50), through one cholmod_update_batched call.  Reports
-    modifications/s and the algorithmic bytes of the batch over its time."""
+    modifications/s and the algorithmic bytes of the batch over its time;
+    then, for one fixed V per factor, the update and the matching downdate
+    batch launched directly and as replays of captured graphs."""
     import random
     import torch
     import paper_1011_1173_amd as chm
@@ -163,6 +165,32 @@ def batched(args):
             byts.append(sum(es * n * (n + 1) + es * n * V.shape[1] for n, V in zip(ns, Vs)))
     ts = sorted(times)
     med = ts[len(ts) // 2]
+    # the same factors with one fixed V each: an update batch and the matching
+    # downdate batch, launched directly and as replays of captured graphs
+    Vfix = [new_v(n) for n in ns]
+    torch.cuda.synchronize()
+    up, down = chm.BatchGraph(Ls, Vfix, [1] * nf), chm.BatchGraph(Ls, Vfix, [-1] * nf)
+    direct_ms, graph_ms = [], []
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup + args.steps):
+            for use_graph in (False, True):
+                for sgn, g in ((1, up), (-1, down)):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    if use_graph:
+                        g.launch(stream)
+                    else:
+                        pb = chm.update_batched_async(Ls, Vfix, [sgn] * nf, stream=stream)
+                    e1.record(stream)
+                    stat = g.statuses() if use_graph else pb.statuses()
+                    assert all(x[0] == 0 for x in stat), stat
+                    if i >= args.warmup:
+                        (graph_ms if use_graph else direct_ms).append(e0.elapsed_time(e1))
+    up.close()
+    down.close()
+    gmed = sorted(graph_ms)[len(graph_ms) // 2]
+    dmed = sorted(direct_ms)[len(direct_ms) // 2]
     out = {"metric": "batched modifications/s (256 uneven factors per call)",
            "value": nf / (med * 1e-3), "unit": "modifications/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": med,
@@ -171,7 +199,8 @@ def batched(args):
                                   "update or downdate 50/50 per factor",
                       "dense_GB": sum(es * n * n for n in ns) / 1e9},
            "batch_ms": {"median": med, "min": ts[0], "max": ts[-1]},
-           "effective_GBps": (sum(byts) / len(byts)) / (med * 1e-3) / 1e9}
+           "effective_GBps": (sum(byts) / len(byts)) / (med * 1e-3) / 1e9,
+           "fixed_batch_ms": {"direct_launch": dmed, "graph_replay": gmed}}
     print(json.dumps(out))
     return 0
 

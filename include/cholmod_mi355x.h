@@ -194,6 +194,30 @@ int cholmod_update_batched(const cholmod_desc *descs, int64_t count, void *ws, s
                            int64_t *d_info, cholmod_stream_t stream);
 
 /*
+ * A batch captured once as a HIP graph and replayed: for a fixed set of
+ * factors (the same descriptors, pointers and sizes) modified again and
+ * again, e.g. serving slots whose L and V contents change between calls.
+ * cholmod_batch_graph_create plans the batch, uploads its tables to `ws`
+ * (synchronously) and captures the preparation launch and the per-step
+ * launches of cholmod_update_batched; cholmod_batch_graph_launch enqueues
+ * one replay on `stream`, which modifies every factor by its V and sigma as
+ * cholmod_update_batched would (bit for bit the same result), reading the
+ * current contents of L and V.  The graph holds kernel launches only.
+ *   descs, count, ws, d_info  as for cholmod_update_batched (count >= 1);
+ *           the graph keeps ws, d_info and every factor's L and V pointer:
+ *           they must stay valid until cholmod_batch_graph_destroy
+ * Replays of one graph share its workspace: replays that overlap in time
+ * (on different streams) race; replays on one stream are ordered.
+ * Returns CHOLMOD_OK, CHOLMOD_ERR_ARG (nothing created or enqueued) or
+ * CHOLMOD_ERR_HIP.
+ */
+typedef struct cholmod_batch_graph cholmod_batch_graph;
+int cholmod_batch_graph_create(const cholmod_desc *descs, int64_t count, void *ws,
+                               size_t ws_bytes, int64_t *d_info, cholmod_batch_graph **out);
+int cholmod_batch_graph_launch(cholmod_batch_graph *g, cholmod_stream_t stream);
+int cholmod_batch_graph_destroy(cholmod_batch_graph *g);
+
+/*
  * Out-of-core modification of a factor held in HOST memory (the paper keeps
  * only O(n) of L on the GPU, Section 4; here for factors larger than HBM).
  * L is streamed through the device in row panels of 64 rows: panel b

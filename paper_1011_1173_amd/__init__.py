@@ -19,7 +19,7 @@ from ._native import (ERR_ARG, ERR_BAD_DIAG, ERR_HIP, ERR_NOT_PD, F32S, F64, FLA
                       FLAG_EXACT, INFO_NONE, OK, LibraryMissing)
 
 __all__ = ["update", "update_async", "update_batched", "update_batched_async",
-           "update_ooc", "workspace_bytes", "workspace_bytes_ooc", "CholmodError", "ArgumentError", "NotPositiveDefinite",
+           "update_ooc", "workspace_bytes", "workspace_bytes_ooc", "BatchGraph", "CholmodError", "ArgumentError", "NotPositiveDefinite",
            "BadDiagonal", "HipError", "LibraryMissing", "Pending", "PendingBatch", "Server"]
 
 
@@ -261,6 +261,59 @@ def update_batched(Ls, Vs, sigmas, *, stream=None):
     (a numerical failure in one factor does not raise and does not affect
     the others)."""
     return update_batched_async(Ls, Vs, sigmas, stream=stream).statuses()
+
+
+class BatchGraph:
+    """A batch captured once as a HIP graph (cholmod_batch_graph_*) and
+    replayed by ``launch``: each replay modifies every factor Ls[i] by
+    (Vs[i], sigmas[i]) from their current contents.  Keeps the tensors, the
+    workspace and the info words alive until ``close``."""
+
+    def __init__(self, Ls, Vs, sigmas):
+        arr, ks, dev = _descs(Ls, Vs, sigmas)
+        count = len(ks)
+        if count == 0:
+            raise ArgumentError("empty batch")
+        lib = _native.load()
+        need = int(lib.cholmod_workspace_bytes_batched(arr, count))
+        if need == 0:
+            raise ArgumentError("invalid batch")
+        self._keep = (list(Ls), list(Vs))
+        self.ks, self.device = ks, dev
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.info = torch.empty(count, dtype=torch.int64, device=dev)
+        h = ctypes.c_void_p()
+        st = lib.cholmod_batch_graph_create(arr, count, ctypes.c_void_p(self.workspace.data_ptr()),
+                                            need, ctypes.c_void_p(self.info.data_ptr()),
+                                            ctypes.byref(h))
+        _raise_for(st)
+        self._h = h
+
+    def launch(self, stream=None):
+        """Enqueue one replay on ``stream`` (default: the current stream)."""
+        if self._h is None:
+            raise ArgumentError("graph closed")
+        stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        _raise_for(_native.load().cholmod_batch_graph_launch(self._h, _stream_handle(stream)))
+        self.stream = stream
+
+    def statuses(self):
+        """Wait for the last replay's stream; (status, row, col) per factor."""
+        self.stream.synchronize()
+        raw = self.info.cpu().tolist()
+        return [_native.decode_info(int(r), k) for r, k in zip(raw, self.ks)]
+
+    def close(self):
+        if self._h is not None:
+            torch.cuda.synchronize(self.device)
+            _native.load().cholmod_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -23,6 +23,7 @@ EXPORTS = (
     "cholmod_update_ex", "cholmod_update_f32s", "cholmod_update_f32s_async",
     "cholmod_workspace_bytes_batched", "cholmod_update_batched",
     "cholmod_workspace_bytes_ooc", "cholmod_update_ooc",
+    "cholmod_batch_graph_create", "cholmod_batch_graph_launch", "cholmod_batch_graph_destroy",
     "cholmod_server_create", "cholmod_server_add_factor", "cholmod_server_submit",
     "cholmod_server_poll", "cholmod_server_drain", "cholmod_server_destroy",
 )
@@ -84,6 +85,12 @@ def load():
     lib.cholmod_workspace_bytes_batched.argtypes = [dp, i64]
     lib.cholmod_workspace_bytes_batched.restype = sz
     lib.cholmod_update_batched.argtypes = [dp, i64, p, sz, p, p]
+    lib.cholmod_batch_graph_create.argtypes = [dp, i64, p, sz, p, ctypes.POINTER(p)]
+    lib.cholmod_batch_graph_create.restype = ci
+    lib.cholmod_batch_graph_launch.argtypes = [p, p]
+    lib.cholmod_batch_graph_launch.restype = ci
+    lib.cholmod_batch_graph_destroy.argtypes = [p]
+    lib.cholmod_batch_graph_destroy.restype = ci
     lib.cholmod_update_batched.restype = ci
     lib.cholmod_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(p)]
     lib.cholmod_server_create.restype = ci

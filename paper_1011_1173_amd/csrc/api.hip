@@ -324,6 +324,12 @@ size_t batch_workspace_bytes(const cholmod_desc* descs, int64_t count) {
   return P.total;
 }
 
+// The batch tables of plan P (built for workspace ws) in host memory at h.
+void write_tables(const BatchPlan& P, char* h) {
+  std::memcpy(h, P.fac.data(), P.fac.size() * sizeof(BatchFactor));
+  if (!P.ent.empty()) std::memcpy(h + P.off_ent, P.ent.data(), P.ent.size() * sizeof(BatchEntry));
+}
+
 int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_bytes,
                   int64_t* d_info, hipStream_t st, void* stage, size_t stage_bytes) {
   BatchPlan P;
@@ -338,8 +344,7 @@ int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_
   if (rc) return rc;
   for (int64_t f = 0; f < count; ++f) P.fac[f].info = d_info + f;
   char* h = (char*)stage;
-  std::memcpy(h, P.fac.data(), P.fac.size() * sizeof(BatchFactor));
-  if (!P.ent.empty()) std::memcpy(h + P.off_ent, P.ent.data(), P.ent.size() * sizeof(BatchEntry));
+  write_tables(P, h);
   if (hipMemcpyAsync(ws, h, P.table_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
     return CHOLMOD_ERR_HIP;
   const BatchFactor* d_fac = (const BatchFactor*)ws;
@@ -613,6 +618,65 @@ int cholmod_update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_
                        cholmod_stream_t stream) {
   return update_ooc(L_host, V, n, k, ldl, sigma, dtype, ws, ws_bytes, (hipStream_t)stream,
                     info);
+}
+
+struct cholmod_batch_graph {
+  hipGraphExec_t exec = nullptr;
+};
+
+int cholmod_batch_graph_create(const cholmod_desc* descs, int64_t count, void* ws,
+                               size_t ws_bytes, int64_t* d_info, cholmod_batch_graph** out) {
+  if (out == nullptr) return CHOLMOD_ERR_ARG;
+  *out = nullptr;
+  if (count < 1) return CHOLMOD_ERR_ARG;
+  const size_t tb = batch_table_bytes(descs, count);
+  const size_t need = batch_workspace_bytes(descs, count);
+  if (tb == 0 || need == 0) return CHOLMOD_ERR_ARG;
+  if (d_info == nullptr || ((uintptr_t)d_info & 7u) != 0) return CHOLMOD_ERR_ARG;
+  if (ws == nullptr || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return CHOLMOD_ERR_ARG;
+  BatchPlan P;
+  int rc = plan_batch(descs, count, (char*)ws, &P);
+  if (rc) return rc;
+  for (int64_t f = 0; f < count; ++f) P.fac[f].info = d_info + f;
+  std::vector<char> tables(P.table_bytes);
+  write_tables(P, tables.data());
+  // the tables stay in the workspace: the graph holds kernel launches only
+  if (hipMemcpy(ws, tables.data(), P.table_bytes, hipMemcpyHostToDevice) != hipSuccess)
+    return CHOLMOD_ERR_HIP;
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  rc = CHOLMOD_ERR_HIP;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess) {
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const hipError_t e = run_sysblk_batch(cs, (const BatchFactor*)ws, count,
+                                            (const BatchEntry*)((char*)ws + P.off_ent),
+                                            P.steps.data(), (int64_t)P.steps.size());
+      const hipError_t ee = hipStreamEndCapture(cs, &graph);
+      if (e == hipSuccess && ee == hipSuccess && graph != nullptr &&
+          hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess)
+        rc = CHOLMOD_OK;
+    }
+    hipStreamDestroy(cs);
+  }
+  if (graph) hipGraphDestroy(graph);
+  if (rc) return rc;
+  *out = new cholmod_batch_graph;
+  (*out)->exec = exec;
+  return CHOLMOD_OK;
+}
+
+int cholmod_batch_graph_launch(cholmod_batch_graph* g, cholmod_stream_t stream) {
+  if (g == nullptr || g->exec == nullptr) return CHOLMOD_ERR_ARG;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? CHOLMOD_OK
+                                                                     : CHOLMOD_ERR_HIP;
+}
+
+int cholmod_batch_graph_destroy(cholmod_batch_graph* g) {
+  if (g == nullptr) return CHOLMOD_OK;
+  const hipError_t e = g->exec ? hipGraphExecDestroy(g->exec) : hipSuccess;
+  delete g;
+  return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
 }
 
 size_t cholmod_workspace_bytes_batched(const cholmod_desc* descs, int64_t count) {

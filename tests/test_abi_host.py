@@ -200,3 +200,22 @@ def test_ooc_python_binding_rejects_bad_tensors():
         chm.update_ooc(L, torch.zeros(4, 2, dtype=torch.float64), 1)   # V on the host
     with pytest.raises(chm.ArgumentError):
         chm.update_ooc(L.float(), torch.zeros(4, 2, dtype=torch.float64), 1)
+
+
+def test_batch_graph_bad_arguments_rejected_on_host(nat):
+    lib = nat.load()
+    p = ctypes.c_void_p
+    h = p()
+    d = nat.Desc(256, 256, 100, 4, 100, 1, nat.F64)
+    arr = (nat.Desc * 1)(d)
+    need = lib.cholmod_workspace_bytes_batched(arr, 1)
+    assert need > 0
+    assert lib.cholmod_batch_graph_create(arr, 0, p(256), need, p(256), ctypes.byref(h)) == nat.ERR_ARG
+    assert lib.cholmod_batch_graph_create(arr, 1, p(256), need - 1, p(256), ctypes.byref(h)) == nat.ERR_ARG
+    assert lib.cholmod_batch_graph_create(arr, 1, p(256), need, None, ctypes.byref(h)) == nat.ERR_ARG
+    assert lib.cholmod_batch_graph_create(arr, 1, p(257), need, p(256), ctypes.byref(h)) == nat.ERR_ARG
+    assert lib.cholmod_batch_graph_create(arr, 1, p(256), need, p(256), None) == nat.ERR_ARG
+    bad = (nat.Desc * 1)(nat.Desc(256, 256, 100, 4, 99, 1, nat.F64))  # ldl < n
+    assert lib.cholmod_batch_graph_create(bad, 1, p(256), need, p(256), ctypes.byref(h)) == nat.ERR_ARG
+    assert lib.cholmod_batch_graph_launch(None, None) == nat.ERR_ARG
+    assert lib.cholmod_batch_graph_destroy(None) == nat.OK
