@@ -79,3 +79,28 @@ def test_graph_update_downdate_cycle_and_failure_status():
     finally:
         up.close()
         down.close()
+
+
+def test_graph_mixed_storage_and_closed_handle():
+    """FP64 and FP32-storage factors in one captured batch; a closed graph
+    refuses to launch."""
+    import paper_1011_1173_amd as chm
+    print_case("graph-mixed")
+    shapes = [(300, 7, False), (450, 16, True), (65, 3, True), (900, 20, False)]
+    Ls, Vs = [], []
+    for f, (n, k, f32) in enumerate(shapes):
+        dt = torch.float32 if f32 else torch.float64
+        Ls.append(inputs.spd_factor(n, 95 + f, device="cuda").to(dt))
+        Vs.append(inputs.update_vectors(n, k, 95 + f, device="cuda").to(dt))
+    ref = [L.clone() for L in Ls]
+    st = chm.update_batched(ref, Vs, [1] * len(Ls))
+    assert all(x[0] == 0 for x in st)
+    Lg = [L.clone() for L in Ls]
+    g = chm.BatchGraph(Lg, Vs, [1] * len(Ls))
+    g.launch()
+    assert all(x[0] == 0 for x in g.statuses())
+    for a, b in zip(Lg, ref):
+        assert torch.equal(a, b)
+    g.close()
+    with pytest.raises(chm.ArgumentError):
+        g.launch()

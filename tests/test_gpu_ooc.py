@@ -108,3 +108,17 @@ def test_ooc_trivial_sizes():
     assert torch.equal(L, before)
     E = torch.zeros(0, 0, dtype=torch.float64)
     chm.update_ooc(E, torch.zeros(0, 3, dtype=torch.float64, device="cuda"), 1)
+
+
+def test_ooc_four_passes_ragged():
+    """k = 64 (four 16-column passes, every panel streamed four times), ragged n."""
+    import paper_1011_1173_amd as chm
+    n, k = 1000, 64
+    print_case("ooc-k64", n=n, k=k)
+    L = inputs.spd_factor(n, 77, device="cuda").cpu()
+    V = inputs.update_vectors(n, k, 77, device="cuda").cpu()
+    ref, st, _, _ = incore(L, V, 1)
+    assert st == 0
+    Lh = L.pin_memory()
+    chm.update_ooc(Lh, V.cuda(), 1)
+    assert torch.equal(Lh, ref)
