@@ -6,6 +6,7 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <numeric>
 #include <vector>
@@ -330,8 +331,13 @@ void write_tables(const BatchPlan& P, char* h) {
   if (!P.ent.empty()) std::memcpy(h + P.off_ent, P.ent.data(), P.ent.size() * sizeof(BatchEntry));
 }
 
+int64_t batch_steps_of(const cholmod_desc& d) {
+  return (d.n <= 0 || d.k <= 0) ? 0 : ceil_div(d.n, kBlock) * ceil_div(d.k, kPass);
+}
+
 int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_bytes,
-                  int64_t* d_info, hipStream_t st, void* stage, size_t stage_bytes) {
+                  int64_t* d_info, hipStream_t st, void* stage, size_t stage_bytes,
+                  const std::function<int(int64_t)>* after_step) {
   BatchPlan P;
   int rc = plan_batch(descs, count, nullptr, &P);
   if (rc) return rc;
@@ -349,9 +355,18 @@ int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_
     return CHOLMOD_ERR_HIP;
   const BatchFactor* d_fac = (const BatchFactor*)ws;
   const BatchEntry* d_ent = (const BatchEntry*)((char*)ws + P.off_ent);
-  hipError_t e = run_sysblk_batch(st, d_fac, count, d_ent, P.steps.data(),
-                                  (int64_t)P.steps.size());
-  return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
+  if (after_step == nullptr) {
+    hipError_t e = run_sysblk_batch(st, d_fac, count, d_ent, P.steps.data(),
+                                    (int64_t)P.steps.size());
+    return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
+  }
+  if (run_sysblk_batch_prepare(st, d_fac, count) != hipSuccess) return CHOLMOD_ERR_HIP;
+  for (int64_t s = 0; s < (int64_t)P.steps.size(); ++s) {
+    if (run_sysblk_batch_step(st, d_fac, d_ent, P.steps[s]) != hipSuccess) return CHOLMOD_ERR_HIP;
+    rc = (*after_step)(s);
+    if (rc) return rc;
+  }
+  return CHOLMOD_OK;
 }
 
 // ------------------------------------------------------------ out-of-core

@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
+
 #include "../../include/cholmod_mi355x.h"
 
 namespace chm {
@@ -12,10 +14,19 @@ namespace chm {
 size_t batch_table_bytes(const cholmod_desc* descs, int64_t count);
 size_t batch_workspace_bytes(const cholmod_desc* descs, int64_t count);
 
+// Launches of a factor in a batch: its step s runs in the batch's launch s,
+// for s < batch_steps_of(desc); after the launch of its last step the
+// factor's L and info word are final.
+int64_t batch_steps_of(const cholmod_desc& d);
+
 // Validate, build the tables in the pinned host buffer `stage` (at least
 // batch_table_bytes), upload them to `ws` and enqueue the batch on `st`.
-// The caller keeps `stage` unchanged until the upload has run.
+// The caller keeps `stage` unchanged until the upload has run.  With
+// after_step, it is called after the launch of every step s is enqueued (to
+// enqueue more work behind it on `st`); a non-zero return stops and is
+// returned.
 int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_bytes,
-                  int64_t* d_info, hipStream_t st, void* stage, size_t stage_bytes);
+                  int64_t* d_info, hipStream_t st, void* stage, size_t stage_bytes,
+                  const std::function<int(int64_t)>* after_step = nullptr);
 
 }  // namespace chm

@@ -9,12 +9,18 @@
 // workspace, info words and staging buffer, let the next batch be enqueued
 // while the previous one runs.  Admission: a request whose batch workspace
 // would exceed the slot's workspace waits for the next batch; a request that
-// cannot fit even alone fails with CHOLMOD_ERR_ARG.  A request's latency is
-// the host time from its submission to the worker seeing its batch complete.
+// cannot fit even alone fails with CHOLMOD_ERR_ARG.  A request completes when
+// the step that ends its factor's work in the batch has run: after that
+// step's launch the worker enqueues the copy of those factors' info words
+// and an event, so small factors batched with large ones complete early.  A
+// request's latency is the host time from its submission to the worker
+// seeing that event.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <functional>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -48,6 +54,15 @@ struct Factor {
   std::deque<uint64_t> queue;  // tickets not yet launched, in arrival order
 };
 
+// Requests of a batch that complete together: those whose factors end at
+// the same step.
+constexpr int kMaxGroups = 32;
+
+struct Group {
+  hipEvent_t ev = nullptr;
+  std::vector<size_t> idx;  // positions in the slot's batch
+};
+
 struct Slot {
   void* ws = nullptr;
   int64_t* d_info = nullptr;
@@ -58,6 +73,9 @@ struct Slot {
   bool busy = false;
   std::vector<uint64_t> tickets;
   std::vector<int64_t> ks;
+  std::vector<char> retired;  // per position in the batch
+  Group groups[kMaxGroups];
+  int ngroups = 0, next_group = 0;
 };
 
 }  // namespace
@@ -88,6 +106,9 @@ struct cholmod_server {
         return CHOLMOD_ERR_HIP;
       if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
         return CHOLMOD_ERR_HIP;
+      for (Group& g : s.groups)
+        if (hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess)
+          return CHOLMOD_ERR_HIP;
     }
     return CHOLMOD_OK;
   }
@@ -99,26 +120,47 @@ struct cholmod_server {
       if (s.h_info) hipHostFree(s.h_info);
       if (s.stage) hipHostFree(s.stage);
       if (s.done) hipEventDestroy(s.done);
+      for (Group& g : s.groups)
+        if (g.ev) hipEventDestroy(g.ev);
       s = Slot{};
     }
     if (stream) hipStreamDestroy(stream);
     stream = nullptr;
   }
 
-  // Requests of a finished slot get their status and latency.
-  void retire(Slot& s, Clock::time_point now) {
-    for (size_t i = 0; i < s.tickets.size(); ++i) {
-      auto it = reqs.find(s.tickets[i]);
-      if (it == reqs.end()) continue;
-      Request& r = it->second;
-      r.status = cholmod_decode_info(s.h_info[i], s.ks[i], nullptr, nullptr);
-      r.latency = std::chrono::duration<double>(now - r.t_submit).count();
-      r.done = true;
+  // Request at position i of slot s gets its status and latency.
+  void retire_one(Slot& s, size_t i, Clock::time_point now) {
+    if (s.retired[i]) return;
+    s.retired[i] = 1;
+    --in_flight;
+    auto it = reqs.find(s.tickets[i]);
+    if (it == reqs.end()) return;
+    Request& r = it->second;
+    r.status = cholmod_decode_info(s.h_info[i], s.ks[i], nullptr, nullptr);
+    r.latency = std::chrono::duration<double>(now - r.t_submit).count();
+    r.done = true;
+  }
+
+  // Groups whose events have fired, in step order; then the whole slot.
+  bool poll_slot(Slot& s) {
+    bool progress = false;
+    while (s.next_group < s.ngroups && hipEventQuery(s.groups[s.next_group].ev) == hipSuccess) {
+      const Clock::time_point now = Clock::now();
+      for (size_t i : s.groups[s.next_group].idx) retire_one(s, i, now);
+      ++s.next_group;
+      progress = true;
     }
-    in_flight -= (int64_t)s.tickets.size();
-    s.tickets.clear();
-    s.ks.clear();
-    s.busy = false;
+    if (hipEventQuery(s.done) == hipSuccess) {
+      const Clock::time_point now = Clock::now();
+      for (size_t i = 0; i < s.tickets.size(); ++i) retire_one(s, i, now);
+      s.tickets.clear();
+      s.ks.clear();
+      s.retired.clear();
+      s.ngroups = s.next_group = 0;
+      s.busy = false;
+      progress = true;
+    }
+    return progress;
   }
 
   // Build and enqueue one batch into slot `s` (lock held).  Returns false
@@ -174,8 +216,43 @@ struct cholmod_server {
       }
       s.stage_bytes = tb;
     }
+    // completion groups: the requests whose factors end at the same step
+    // (factors without steps are final after the preparation launch, so with
+    // those of step 0); beyond kMaxGroups - 1 distinct steps the rest
+    // complete with the slot
+    std::vector<int64_t> last(count);
+    std::vector<int64_t> ends;
+    for (int64_t i = 0; i < count; ++i) {
+      const int64_t st_i = chm::batch_steps_of(descs[i]);
+      last[i] = st_i > 0 ? st_i - 1 : 0;
+      ends.push_back(last[i]);
+    }
+    std::sort(ends.begin(), ends.end());
+    ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
+    if ((int)ends.size() > kMaxGroups - 1) ends.resize(kMaxGroups - 1);
+    s.ngroups = (int)ends.size();
+    s.next_group = 0;
+    for (int g = 0; g < s.ngroups; ++g) s.groups[g].idx.clear();
+    for (int64_t i = 0; i < count; ++i) {
+      const auto it = std::lower_bound(ends.begin(), ends.end(), last[i]);
+      if (it != ends.end() && *it == last[i]) s.groups[it - ends.begin()].idx.push_back((size_t)i);
+    }
+    int g_next = 0;
+    const std::function<int(int64_t)> after_step = [&](int64_t step) -> int {
+      while (g_next < s.ngroups && ends[g_next] == step) {
+        for (size_t i : s.groups[g_next].idx)
+          if (hipMemcpyAsync(s.h_info + i, s.d_info + i, sizeof(int64_t), hipMemcpyDeviceToHost,
+                             stream) != hipSuccess)
+            return CHOLMOD_ERR_HIP;
+        if (hipEventRecord(s.groups[g_next].ev, stream) != hipSuccess) return CHOLMOD_ERR_HIP;
+        ++g_next;
+      }
+      return CHOLMOD_OK;
+    };
     int rc = chm::enqueue_batch(descs.data(), count, s.ws, cfg.ws_bytes, s.d_info, stream,
-                                s.stage, s.stage_bytes);
+                                s.stage, s.stage_bytes, &after_step);
+    // groups never reached (a stopped enqueue) complete with the slot
+    s.ngroups = g_next;
     if (rc == CHOLMOD_OK &&
         hipMemcpyAsync(s.h_info, s.d_info, count * sizeof(int64_t), hipMemcpyDeviceToHost,
                        stream) != hipSuccess)
@@ -193,6 +270,7 @@ struct cholmod_server {
     s.tickets = std::move(tickets);
     s.ks.clear();
     for (const cholmod_desc& d : descs) s.ks.push_back(d.k);
+    s.retired.assign(s.tickets.size(), 0);
     s.busy = true;
     in_flight += count;
     return true;
@@ -204,10 +282,7 @@ struct cholmod_server {
     while (!stop) {
       bool progress = false;
       for (Slot& s : slots) {
-        if (s.busy && hipEventQuery(s.done) == hipSuccess) {
-          retire(s, Clock::now());
-          progress = true;
-        }
+        if (s.busy) progress |= poll_slot(s);
       }
       if (in_queue > 0 && !fatal) {
         for (Slot& s : slots) {
