@@ -271,6 +271,8 @@ int cholmod_server_create(const cholmod_server_cfg *cfg, cholmod_server **out);
 /*
  * Register a device factor (caller-owned, stays valid until the server is
  * destroyed; only the server modifies it meanwhile).  *id receives its index.
+ * CHOLMOD_ERR_ARG for a bad size or dtype, including an n * ldl whose byte
+ * count does not fit in int64.
  */
 int cholmod_server_add_factor(cholmod_server *srv, void *L, int64_t n, int64_t ldl, int dtype,
                               int32_t *id);
@@ -279,6 +281,8 @@ int cholmod_server_add_factor(cholmod_server *srv, void *L, int64_t n, int64_t l
  * Queue the modification of factor `id` by V (device, (n, k) row-major, in
  * the factor's storage type; caller-owned and unchanged until the request
  * completes).  *ticket identifies the request.  Never blocks on the GPU.
+ * CHOLMOD_ERR_ARG (nothing queued) for an unknown id, a bad k or sigma, a
+ * null V, or an n * k whose workspace size does not fit in int64.
  * The server works on its own stream, which waits for no other stream: any
  * GPU work that writes V or the factor must have completed before the call.
  */

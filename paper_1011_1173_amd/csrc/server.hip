@@ -188,8 +188,9 @@ struct cholmod_server {
       const size_t need = chm::batch_workspace_bytes(descs.data(), (int64_t)descs.size());
       if (need == 0 || need > cfg.ws_bytes) {
         descs.pop_back();
-        if (descs.empty() && need > cfg.ws_bytes) {
-          // cannot run even alone
+        if (need == 0 || descs.empty()) {
+          // rejected by the planner, or cannot run even alone: it fails
+          // here rather than staying at the head of its factor's queue
           F.queue.pop_front();
           --in_queue;
           r.status = CHOLMOD_ERR_ARG;
@@ -340,6 +341,16 @@ int cholmod_server_add_factor(cholmod_server* s, void* L, int64_t n, int64_t ldl
   if (s == nullptr || id == nullptr) return CHOLMOD_ERR_ARG;
   if (n < 0 || ldl < (n > 1 ? n : 1) || (n > 0 && L == nullptr)) return CHOLMOD_ERR_ARG;
   if (dtype != CHOLMOD_F64 && dtype != CHOLMOD_F32S) return CHOLMOD_ERR_ARG;
+  // the batch planner's own checks (n * ldl must have a byte count)
+  cholmod_desc d;
+  d.L = L;
+  d.V = nullptr;
+  d.n = n;
+  d.k = 0;
+  d.ldl = ldl;
+  d.sigma = 1;
+  d.dtype = dtype;
+  if (chm::batch_workspace_bytes(&d, 1) == 0) return CHOLMOD_ERR_ARG;
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->factors.size() >= 0x7fffffff) return CHOLMOD_ERR_ARG;
   Factor F;
@@ -361,6 +372,16 @@ int cholmod_server_submit(cholmod_server* s, int32_t id, const void* V, int64_t 
   Factor& F = s->factors[id];
   if (k < 0 || (sigma != 1 && sigma != -1) || (F.n > 0 && k > 0 && V == nullptr))
     return CHOLMOD_ERR_ARG;
+  // the batch planner's own checks (sizes whose byte counts overflow)
+  cholmod_desc d;
+  d.L = F.L;
+  d.V = V;
+  d.n = F.n;
+  d.k = k;
+  d.ldl = F.ldl;
+  d.sigma = sigma;
+  d.dtype = F.dtype;
+  if (chm::batch_workspace_bytes(&d, 1) == 0) return CHOLMOD_ERR_ARG;
   const uint64_t t = s->next_ticket++;
   Request r;
   r.factor = id;

@@ -77,3 +77,29 @@ def test_server_reports_failures_per_request(orc):
     assert s1[0] == chm.ERR_NOT_PD
     assert s2[0] == 0
     assert s3[0] == chm.ERR_ARG  # needs more workspace than one batch slot has
+
+
+def test_server_rejects_overflowing_sizes():
+    """Sizes whose byte counts overflow are refused when the factor is
+    registered or the request submitted, so no request can wait in a queue
+    that no batch will ever take it from (drain would never return)."""
+    import ctypes
+    import paper_1011_1173_amd as chm
+    from paper_1011_1173_amd import _native
+    print_case("server-overflow")
+    lib = _native.load()
+    L = torch.eye(100, dtype=torch.float64, device="cuda")
+    V = torch.zeros(100, 1, dtype=torch.float64, device="cuda")
+    with chm.Server(ws_bytes=1 << 20, max_batch=4) as srv:
+        fid = ctypes.c_int32(-1)
+        assert lib.cholmod_server_add_factor(srv._h, ctypes.c_void_p(L.data_ptr()), 100, 1 << 62,
+                                             chm.F64, ctypes.byref(fid)) == chm.ERR_ARG
+        a = srv.add_factor(L)
+        t = ctypes.c_uint64(0)
+        assert lib.cholmod_server_submit(srv._h, a, ctypes.c_void_p(V.data_ptr()), 1 << 60, 1,
+                                         ctypes.byref(t)) == chm.ERR_ARG
+        ok = srv.submit(a, V, +1)
+        srv.drain()
+        assert srv.poll(ok)[0] == 0
+    # V = 0 leaves the identity factor unchanged
+    assert torch.allclose(L, torch.eye(100, dtype=torch.float64, device="cuda"), atol=1e-15)
