@@ -266,8 +266,8 @@ def sweep(args):
 
 
 def ooc(args):
-    """Out-of-core form: the factor in host memory (pinned, and pageable for
-    n = 5000), V on the GPU, k = 16, FP64.  Per configuration one untimed
+    """Out-of-core form: the factor in host memory (pinned or pageable), V on
+    the GPU, k = 16, FP64.  Per configuration one untimed
     update/downdate pair, then 2 timed pairs (wall clock: the call is
     synchronous).  Reports ms per modification, the host<->device bytes
     moved (every 64-row panel of the upper triangle copied in and out once
@@ -281,7 +281,8 @@ def ooc(args):
     torch.cuda.set_device(dev)
     k, es = 16, 8
     rows = []
-    for n, pinned in ((5000, True), (5000, False), (20000, True)):
+    # the headline row (value) is the last one: n = 20000, pinned
+    for n, pinned in ((5000, True), (5000, False), (20000, False), (20000, True)):
         Ld = inputs.spd_factor(n, seed=4, device="cuda")
         V = inputs.update_vectors(n, k, seed=4, device="cuda")
         # device time of the same modification

@@ -228,8 +228,10 @@ int cholmod_batch_graph_destroy(cholmod_batch_graph *g);
  * point of the same storage type gives.  Synchronous: returns when L in
  * host memory holds the result.
  *   L_host  HOST double* (CHOLMOD_F64) or float* (CHOLMOD_F32S), (n, ldl)
- *           row-major upper triangle, modified in place; pinned memory
- *           (hipHostMalloc) copies fastest, pageable memory works
+ *           row-major upper triangle, modified in place.  Pinned memory
+ *           (hipHostMalloc) is copied directly.  Pageable memory goes
+ *           through four pinned host buffers of 64 x n elements that the
+ *           call allocates and frees, packed and unpacked by host threads
  *   V       DEVICE, (n, k) row-major in the storage type, unchanged
  *   ws      device workspace of at least cholmod_workspace_bytes_ooc(n, k,
  *           dtype) bytes, 256-byte aligned; NULL: the call allocates and

@@ -4,11 +4,14 @@
 
 #include <algorithm>
 #include <climits>
+#include <condition_variable>
 #include <cstdint>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <mutex>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "../../include/cholmod_mi355x.h"
@@ -416,6 +419,90 @@ bool ooc_layout(int64_t n, int64_t k, int dtype, OocLayout* out) {
   return true;
 }
 
+// Host memory the copy engines can reach directly (hipHostMalloc'd, which
+// includes torch's pinned tensors).
+bool host_pinned(const void* p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();  // unknown host pointer: not an error here
+    return false;
+  }
+  return a.type == hipMemoryTypeHost;
+}
+
+// Copies `rows` rows of `wbytes` bytes between pitched host buffers, split
+// over the calling thread and a few helper threads that live as long as the
+// object (one out-of-core call).
+class RowCopier {
+ public:
+  explicit RowCopier(int helpers) {
+    for (int t = 0; t < helpers; ++t) th_.emplace_back([this, t] { loop(t + 1); });
+  }
+  ~RowCopier() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      quit_ = true;
+    }
+    cv_.notify_all();
+    for (std::thread& t : th_) t.join();
+  }
+  void run(char* dst, size_t dpitch, const char* src, size_t spitch, size_t wbytes,
+           int64_t rows) {
+    const int parts = wbytes * (size_t)rows >= (1u << 20) ? (int)th_.size() + 1 : 1;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      dst_ = dst;
+      src_ = src;
+      dpitch_ = dpitch;
+      spitch_ = spitch;
+      wbytes_ = wbytes;
+      rows_ = rows;
+      parts_ = parts;
+      pending_ = parts - 1;
+      ++gen_;
+    }
+    if (parts > 1) cv_.notify_all();
+    part(0, parts);
+    std::unique_lock<std::mutex> lk(mu_);
+    done_.wait(lk, [&] { return pending_ == 0; });
+  }
+
+ private:
+  void part(int t, int parts) {
+    const int64_t per = (rows_ + parts - 1) / parts;
+    const int64_t a = t * per, b = std::min(rows_, a + per);
+    for (int64_t r = a; r < b; ++r)
+      std::memcpy(dst_ + r * dpitch_, src_ + r * spitch_, wbytes_);
+  }
+  void loop(int t) {
+    uint64_t seen = 0;
+    for (;;) {
+      int parts;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return quit_ || gen_ != seen; });
+        if (quit_) return;
+        seen = gen_;
+        parts = parts_;
+      }
+      if (t >= parts) continue;  // a small copy: the caller does it alone
+      part(t, parts);
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--pending_ == 0) done_.notify_all();
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_;
+  uint64_t gen_ = 0;
+  int pending_ = 0, parts_ = 1;
+  bool quit_ = false;
+  char* dst_ = nullptr;
+  const char* src_ = nullptr;
+  size_t dpitch_ = 0, spitch_ = 0, wbytes_ = 0;
+  int64_t rows_ = 0;
+};
+
 int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, int sigma,
                int dtype, void* ws, size_t ws_bytes, hipStream_t st, int64_t* info_out) {
   if (info_out) *info_out = CHOLMOD_INFO_NONE;
@@ -480,6 +567,22 @@ int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, i
     // latest out_done record of the slot.
     hipStream_t up = nullptr, down = nullptr;
     hipEvent_t in_done[3] = {}, out_done[3] = {}, step_done = nullptr;
+    // Pageable host memory reaches the copy engines only through the
+    // runtime's own staging, far below the link rate, so such a factor goes
+    // through pinned buffers of this call: host threads pack a panel's rows
+    // into one of two in-buffers before its upload, and unpack a downloaded
+    // panel from one of two out-buffers two downloads later, before the
+    // panel is read again in the next pass, or at the end.  Every host wait
+    // is for copies already enqueued.
+    const bool staged = !host_pinned(L_host);
+    const size_t sbytes = (size_t)(kBlock * n * es);
+    char* sin[2] = {nullptr, nullptr};
+    char* sout[2] = {nullptr, nullptr};
+    hipEvent_t sin_free[2] = {}, sout_full[2] = {};
+    bool sin_used[2] = {false, false};
+    int64_t pend[2] = {-1, -1};  // panel waiting in sout[i] to be unpacked
+    int64_t n_in = 0, n_out = 0;
+    std::unique_ptr<RowCopier> copier;
     auto create = [&]() {
       if (hipStreamCreateWithFlags(&up, hipStreamNonBlocking) != hipSuccess) return false;
       if (hipStreamCreateWithFlags(&down, hipStreamNonBlocking) != hipSuccess) return false;
@@ -488,30 +591,85 @@ int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, i
         if (hipEventCreateWithFlags(&out_done[q], hipEventDisableTiming) != hipSuccess)
           return false;
       }
-      return hipEventCreateWithFlags(&step_done, hipEventDisableTiming) == hipSuccess;
+      if (hipEventCreateWithFlags(&step_done, hipEventDisableTiming) != hipSuccess) return false;
+      if (!staged) return true;
+      for (int i = 0; i < 2; ++i) {
+        if (hipHostMalloc((void**)&sin[i], sbytes, hipHostMallocDefault) != hipSuccess)
+          return false;
+        if (hipHostMalloc((void**)&sout[i], sbytes, hipHostMallocDefault) != hipSuccess)
+          return false;
+        if (hipEventCreateWithFlags(&sin_free[i], hipEventDisableTiming) != hipSuccess)
+          return false;
+        if (hipEventCreateWithFlags(&sout_full[i], hipEventDisableTiming) != hipSuccess)
+          return false;
+      }
+      copier.reset(new RowCopier(3));
+      return true;
     };
-    // rows [b*64, b*64 + rows) of L, columns b*64 .. n-1, to or from its slot
-    auto panel = [&](int64_t b, bool in, hipStream_t cs) {
-      const int64_t r0 = b * kBlock, rows = std::min(kBlock, n - r0);
-      char* dev = (char*)row_base(b) + (r0 * n + r0) * es;
-      char* host = (char*)L_host + (r0 * ldl + r0) * es;
-      const size_t width = (size_t)((n - r0) * es);
-      return in ? hipMemcpy2DAsync(dev, (size_t)(n * es), host, (size_t)(ldl * es), width,
-                                   (size_t)rows, hipMemcpyHostToDevice, cs)
-                : hipMemcpy2DAsync(host, (size_t)(ldl * es), dev, (size_t)(n * es), width,
-                                   (size_t)rows, hipMemcpyDeviceToHost, cs);
+    // rows [b*64, b*64 + rows) of L, columns b*64 .. n-1: in the device slot
+    // (row pitch n), in the host factor (row pitch ldl)
+    auto rows_of = [&](int64_t b) { return std::min(kBlock, n - b * kBlock); };
+    auto width_of = [&](int64_t b) { return (size_t)((n - b * kBlock) * es); };
+    auto dev_panel = [&](int64_t b) {
+      return (char*)row_base(b) + (b * kBlock * n + b * kBlock) * es;
+    };
+    auto host_panel = [&](int64_t b) {
+      return (char*)L_host + (b * kBlock * ldl + b * kBlock) * es;
+    };
+    // the download waiting in sout[i] goes to the host factor
+    auto unpack = [&](int i) {
+      if (pend[i] < 0) return true;
+      if (hipEventSynchronize(sout_full[i]) != hipSuccess) return false;
+      const int64_t b = pend[i];
+      copier->run(host_panel(b), (size_t)(ldl * es), sout[i], width_of(b), width_of(b),
+                  rows_of(b));
+      pend[i] = -1;
+      return true;
+    };
+    auto copy_in = [&](int64_t b) {
+      const int64_t q = b % 3;
+      const size_t wb = width_of(b);
+      if (hipStreamWaitEvent(up, out_done[q], 0) != hipSuccess) return false;
+      if (!staged) {
+        if (hipMemcpy2DAsync(dev_panel(b), (size_t)(n * es), host_panel(b), (size_t)(ldl * es),
+                             wb, (size_t)rows_of(b), hipMemcpyHostToDevice, up) != hipSuccess)
+          return false;
+      } else {
+        const int i = (int)(n_in++ & 1);
+        if (sin_used[i] && hipEventSynchronize(sin_free[i]) != hipSuccess) return false;
+        for (int j = 0; j < 2; ++j)
+          if (pend[j] == b && !unpack(j)) return false;  // the previous pass's result
+        copier->run(sin[i], wb, host_panel(b), (size_t)(ldl * es), wb, rows_of(b));
+        if (hipMemcpy2DAsync(dev_panel(b), (size_t)(n * es), sin[i], wb, wb, (size_t)rows_of(b),
+                             hipMemcpyHostToDevice, up) != hipSuccess ||
+            hipEventRecord(sin_free[i], up) != hipSuccess)
+          return false;
+        sin_used[i] = true;
+      }
+      return hipEventRecord(in_done[q], up) == hipSuccess;
     };
     auto copy_out = [&](int64_t b) {
+      const size_t wb = width_of(b);
       if (hipStreamWaitEvent(down, step_done, 0) != hipSuccess) return false;
-      if (panel(b, false, down) != hipSuccess) return false;
+      if (!staged) {
+        if (hipMemcpy2DAsync(host_panel(b), (size_t)(ldl * es), dev_panel(b), (size_t)(n * es),
+                             wb, (size_t)rows_of(b), hipMemcpyDeviceToHost, down) != hipSuccess)
+          return false;
+      } else {
+        const int i = (int)(n_out++ & 1);
+        if (!unpack(i)) return false;
+        if (hipMemcpy2DAsync(sout[i], wb, dev_panel(b), (size_t)(n * es), wb, (size_t)rows_of(b),
+                             hipMemcpyDeviceToHost, down) != hipSuccess ||
+            hipEventRecord(sout_full[i], down) != hipSuccess)
+          return false;
+        pend[i] = b;
+      }
       return hipEventRecord(out_done[b % 3], down) == hipSuccess;
     };
     bool good = create();
     for (int64_t s = 0; good && s < (int64_t)P.steps.size(); ++s) {
       const int64_t b = s % nb, q = b % 3;
-      good = hipStreamWaitEvent(up, out_done[q], 0) == hipSuccess &&
-             panel(b, true, up) == hipSuccess && hipEventRecord(in_done[q], up) == hipSuccess &&
-             hipStreamWaitEvent(st, in_done[q], 0) == hipSuccess &&
+      good = copy_in(b) && hipStreamWaitEvent(st, in_done[q], 0) == hipSuccess &&
              run_sysblk_batch_step(st, d_fac, d_ent, P.steps[s]) == hipSuccess &&
              hipEventRecord(step_done, st) == hipSuccess;
       if (good && b > 0) good = copy_out(b - 1);
@@ -522,6 +680,15 @@ int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, i
     if (good && nb > 1) good = hipStreamWaitEvent(st, out_done[(nb - 2) % 3], 0) == hipSuccess;
     if (up && hipStreamSynchronize(up) != hipSuccess) good = false;
     if (down && hipStreamSynchronize(down) != hipSuccess) good = false;
+    // the older pending download first
+    if (good && staged) good = unpack((int)(n_out & 1)) && unpack((int)((n_out + 1) & 1));
+    copier.reset();
+    for (int i = 0; i < 2; ++i) {
+      if (sin[i]) hipHostFree(sin[i]);
+      if (sout[i]) hipHostFree(sout[i]);
+      if (sin_free[i]) hipEventDestroy(sin_free[i]);
+      if (sout_full[i]) hipEventDestroy(sout_full[i]);
+    }
     for (int q = 0; q < 3; ++q) {
       if (in_done[q]) hipEventDestroy(in_done[q]);
       if (out_done[q]) hipEventDestroy(out_done[q]);

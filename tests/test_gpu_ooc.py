@@ -24,6 +24,11 @@ def incore(L, V, sigma):
     (1, 1, 1, None, False), (5, 3, -1, None, False), (64, 16, 1, None, True),
     (65, 4, -1, None, False), (200, 5, 1, 203, True), (300, 16, -1, None, False),
     (300, 33, 1, None, True), (1000, 16, 1, None, True), (3000, 16, -1, None, True),
+    # pageable factors go through the library's pinned staging buffers: one
+    # and two blocks over three passes (a panel is read again while its last
+    # download may still wait to be unpacked), a ragged ldl, larger sizes
+    (64, 33, 1, None, False), (100, 40, -1, None, False), (130, 17, 1, 131, False),
+    (1000, 33, -1, 1003, False), (3000, 16, 1, None, False),
 ])
 def test_ooc_equals_incore_bitwise(n, k, sigma, ldl, pinned):
     import paper_1011_1173_amd as chm
