@@ -235,7 +235,7 @@ int cholmod_batch_graph_destroy(cholmod_batch_graph *g);
  *   V       DEVICE, (n, k) row-major in the storage type, unchanged
  *   ws      device workspace of at least cholmod_workspace_bytes_ooc(n, k,
  *           dtype) bytes, 256-byte aligned; NULL: the call allocates and
- *           frees it.  Device memory used: 3 panels of 64 x n elements plus
+ *           frees it.  Device memory used: 6 panels of 64 x n elements plus
  *           V's copy and the rotation records, O(n (64 + k)).
  *   info    HOST int64* (may be NULL): the raw info word
  * Returns CHOLMOD_OK, CHOLMOD_ERR_NOT_PD / CHOLMOD_ERR_BAD_DIAG (L's rows at

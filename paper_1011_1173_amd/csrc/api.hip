@@ -378,11 +378,14 @@ int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_
 // schedule (one launch per block step); step b touches only the rows of
 // blocks b and b-1, so panel b is uploaded before step b and downloaded
 // after step b+1 (or after step b for the last block of a pass).  Panel p
-// lives in slot p mod 3, so the upload of panel b never overwrites a panel
-// still in use; a slot holds 64 rows of n elements (row pitch n) and keeps
-// the column index of the factor.
+// lives in slot p mod kOocSlots; three slots would suffice (the upload of
+// panel b never overwrites panels b-1 and b), more let the uploads run
+// further ahead of the steps.  A slot holds 64 rows of n elements (row pitch
+// n) and keeps the column index of the factor.
 //   workspace = [batch workspace of the factor (row pitch n)] [info word]
-//               [3 slots of 64 x n elements]
+//               [kOocSlots slots of 64 x n elements]
+constexpr int kOocSlots = 6;
+
 struct OocLayout {
   size_t batch = 0, info = 0, slots = 0, slot_bytes = 0, total = 0;
 };
@@ -414,7 +417,7 @@ bool ooc_layout(int64_t n, int64_t k, int dtype, OocLayout* out) {
   L.info = align_up(batch);
   L.slots = L.info + kAlign;
   L.slot_bytes = align_up((size_t)(kBlock * (n > 1 ? n : 1)) * es);
-  L.total = L.slots + 3 * L.slot_bytes;
+  L.total = L.slots + kOocSlots * L.slot_bytes;
   *out = L;
   return true;
 }
@@ -533,7 +536,7 @@ int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, i
     // device address of element (b * 64, 0) of a panel: slot base minus the
     // rows before the block, so the kernels index rows and columns as in L
     auto row_base = [&](int64_t b) -> void* {
-      const uintptr_t slot = slots + (uintptr_t)(b % 3) * lay.slot_bytes;
+      const uintptr_t slot = slots + (uintptr_t)(b % kOocSlots) * lay.slot_bytes;
       return (void*)(slot - (uintptr_t)(b * kBlock * n * es));
     };
     P.fac[0].L = nullptr;  // the entries carry the panel addresses
@@ -566,7 +569,7 @@ int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, i
     // out of the previous pass: both are ordered on `down` before the
     // latest out_done record of the slot.
     hipStream_t up = nullptr, down = nullptr;
-    hipEvent_t in_done[3] = {}, out_done[3] = {}, step_done = nullptr;
+    hipEvent_t in_done[kOocSlots] = {}, out_done[kOocSlots] = {}, step_done = nullptr;
     // Pageable host memory reaches the copy engines only through the
     // runtime's own staging, far below the link rate, so such a factor goes
     // through pinned buffers of this call: host threads pack a panel's rows
@@ -586,7 +589,7 @@ int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, i
     auto create = [&]() {
       if (hipStreamCreateWithFlags(&up, hipStreamNonBlocking) != hipSuccess) return false;
       if (hipStreamCreateWithFlags(&down, hipStreamNonBlocking) != hipSuccess) return false;
-      for (int q = 0; q < 3; ++q) {
+      for (int q = 0; q < kOocSlots; ++q) {
         if (hipEventCreateWithFlags(&in_done[q], hipEventDisableTiming) != hipSuccess) return false;
         if (hipEventCreateWithFlags(&out_done[q], hipEventDisableTiming) != hipSuccess)
           return false;
@@ -627,7 +630,7 @@ int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, i
       return true;
     };
     auto copy_in = [&](int64_t b) {
-      const int64_t q = b % 3;
+      const int64_t q = b % kOocSlots;
       const size_t wb = width_of(b);
       if (hipStreamWaitEvent(up, out_done[q], 0) != hipSuccess) return false;
       if (!staged) {
@@ -664,11 +667,11 @@ int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, i
           return false;
         pend[i] = b;
       }
-      return hipEventRecord(out_done[b % 3], down) == hipSuccess;
+      return hipEventRecord(out_done[b % kOocSlots], down) == hipSuccess;
     };
     bool good = create();
     for (int64_t s = 0; good && s < (int64_t)P.steps.size(); ++s) {
-      const int64_t b = s % nb, q = b % 3;
+      const int64_t b = s % nb, q = b % kOocSlots;
       good = copy_in(b) && hipStreamWaitEvent(st, in_done[q], 0) == hipSuccess &&
              run_sysblk_batch_step(st, d_fac, d_ent, P.steps[s]) == hipSuccess &&
              hipEventRecord(step_done, st) == hipSuccess;
@@ -676,8 +679,10 @@ int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, i
       if (good && b == nb - 1) good = copy_out(b);
     }
     // the caller's stream waits for the last copies out
-    if (good && nb > 0) good = hipStreamWaitEvent(st, out_done[(nb - 1) % 3], 0) == hipSuccess;
-    if (good && nb > 1) good = hipStreamWaitEvent(st, out_done[(nb - 2) % 3], 0) == hipSuccess;
+    if (good && nb > 0)
+      good = hipStreamWaitEvent(st, out_done[(nb - 1) % kOocSlots], 0) == hipSuccess;
+    if (good && nb > 1)
+      good = hipStreamWaitEvent(st, out_done[(nb - 2) % kOocSlots], 0) == hipSuccess;
     if (up && hipStreamSynchronize(up) != hipSuccess) good = false;
     if (down && hipStreamSynchronize(down) != hipSuccess) good = false;
     // the older pending download first
@@ -689,7 +694,7 @@ int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, i
       if (sin_free[i]) hipEventDestroy(sin_free[i]);
       if (sout_full[i]) hipEventDestroy(sout_full[i]);
     }
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < kOocSlots; ++q) {
       if (in_done[q]) hipEventDestroy(in_done[q]);
       if (out_done[q]) hipEventDestroy(out_done[q]);
     }
