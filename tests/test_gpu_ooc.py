@@ -57,15 +57,16 @@ def test_ooc_matches_oracle(orc):
     assert rel_diff(Lh.numpy(), ref) <= RESID_TOL
 
 
-def test_ooc_f32_storage_equals_incore_bitwise():
+@pytest.mark.parametrize("pinned", [True, False])
+def test_ooc_f32_storage_equals_incore_bitwise(pinned):
     import paper_1011_1173_amd as chm
     n, k = 500, 16
-    print_case("ooc-f32s", n=n, k=k)
+    print_case("ooc-f32s", n=n, k=k, pinned=pinned)
     L = inputs.spd_factor(n, 73, device="cuda").float().cpu()
     V = inputs.update_vectors(n, k, 73, device="cuda").float().cpu()
     ref, st, _, _ = incore(L, V, 1)
     assert st == 0
-    Lh = L.pin_memory()
+    Lh = L.pin_memory() if pinned else L.clone()
     chm.update_ooc(Lh, V.cuda(), 1)
     assert torch.equal(Lh, ref)
 
