@@ -136,6 +136,29 @@ int cholmod_update_ex(double *L, const double *V, int64_t n, int64_t k, int64_t 
                       int64_t *d_info, cholmod_stream_t stream);
 
 /*
+ * Allocation-free form of cholmod_update_async, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  The same modification and kernels as
+ * cholmod_update_async, bit for bit the same result, but the workspace is a
+ * fixed device array inside the library (cholmod_noalloc_max_bytes() bytes,
+ * 32 MiB), one copy per device, held until the process ends; the call
+ * allocates nothing.  The caller passes L, V, the device info word d_info
+ * (raw info word, decode with cholmod_decode_info) and the stream.
+ *   Limit: cholmod_workspace_bytes(n, k, CHOLMOD_F64) must not exceed
+ *   cholmod_noalloc_max_bytes() (n = 5000, k = 16 needs 3.2 MB; at k = 16,
+ *   n up to about 52000); larger problems return CHOLMOD_ERR_ARG before
+ *   any HIP call.
+ * Every call on one device shares that device's array: calls that overlap
+ * in time on one device (different streams, or host threads) race and
+ * give undefined results; calls ordered on one stream are safe.  Each call
+ * re-initialises every part of the array it uses.
+ * Returns CHOLMOD_OK if enqueued, CHOLMOD_ERR_ARG, or CHOLMOD_ERR_HIP.
+ */
+size_t cholmod_noalloc_max_bytes(void);
+int cholmod_update_noalloc(double *L, const double *V, int64_t n, int64_t k, int64_t ldl,
+                           int sigma, int64_t *d_info, cholmod_stream_t stream);
+
+/*
  * FP32-storage mode: the same modification (Algorithm 1) with L and V
  * stored in binary32.  The rows of each 64-row diagonal block -- every
  * Compute (w, c, s, 1/c) and the Apply inside the block -- are evaluated in

@@ -26,6 +26,7 @@ EXPORTS = (
     "cholmod_batch_graph_create", "cholmod_batch_graph_launch", "cholmod_batch_graph_destroy",
     "cholmod_server_create", "cholmod_server_add_factor", "cholmod_server_submit",
     "cholmod_server_poll", "cholmod_server_drain", "cholmod_server_destroy",
+    "cholmod_noalloc_max_bytes", "cholmod_update_noalloc",
 )
 
 
@@ -72,6 +73,10 @@ def load():
     lib.cholmod_update_async.restype = ci
     lib.cholmod_update_ex.argtypes = [p, p, i64, i64, i64, ci, cu, p, sz, p, p]
     lib.cholmod_update_ex.restype = ci
+    lib.cholmod_noalloc_max_bytes.argtypes = []
+    lib.cholmod_noalloc_max_bytes.restype = sz
+    lib.cholmod_update_noalloc.argtypes = [p, p, i64, i64, i64, ci, p, p]
+    lib.cholmod_update_noalloc.restype = ci
     lib.cholmod_update_f32s.argtypes = [p, p, i64, i64, i64, ci, p]
     lib.cholmod_update_f32s.restype = ci
     lib.cholmod_update_f32s_async.argtypes = [p, p, i64, i64, i64, ci, p, sz, p, p]

@@ -210,6 +210,34 @@ int run_sync(int64_t n, int64_t k, int dtype, hipStream_t st, Enqueue enqueue) {
   return cholmod_decode_info(*d.host_info, k, nullptr, nullptr);
 }
 
+// ----------------------------------------------------- allocation-free form
+// cholmod_update_noalloc keeps its workspace in this fixed device array
+// instead of a caller buffer.  Each device that runs the library holds its
+// own copy until the process ends.  In host code `scratch` only names the
+// symbol: its device address on the current device comes from
+// hipGetSymbolAddress, looked up once per device and kept in g_scratch.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of the scratch array on device `dev`, or nullptr.
+void* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch[dev] = p;
+  }
+  return g_scratch[dev];
+}
+
 // ------------------------------------------------------------------ batched
 constexpr int64_t kBlock = 64, kPass = 16, kMaxBatch = 65535;
 
@@ -776,6 +804,23 @@ int cholmod_update(double* L, const double* V, int64_t n, int64_t k, int64_t ldl
                   [&](void* ws, size_t bytes, int64_t* d_info, hipStream_t st) {
                     return enqueue_f64(L, V, n, k, ldl, sigma, 0u, ws, bytes, d_info, st);
                   });
+}
+
+size_t cholmod_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int cholmod_update_noalloc(double* L, const double* V, int64_t n, int64_t k, int64_t ldl,
+                           int sigma, int64_t* d_info, cholmod_stream_t stream) {
+  // every check before any HIP call
+  const int v = validate(L, V, n, k, ldl, sigma);
+  if (v) return v;
+  if (d_info == nullptr || ((uintptr_t)d_info & 7u) != 0) return CHOLMOD_ERR_ARG;
+  WsLayout lay;
+  if (!layout_for(n, k, CHOLMOD_F64, &lay) || lay.total > kScratchBytes) return CHOLMOD_ERR_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CHOLMOD_ERR_HIP;
+  void* ws = scratch_address(dev);
+  if (ws == nullptr) return CHOLMOD_ERR_HIP;
+  return enqueue_f64(L, V, n, k, ldl, sigma, 0u, ws, kScratchBytes, d_info, (hipStream_t)stream);
 }
 
 int cholmod_update_f32s_async(float* L, const float* V, int64_t n, int64_t k, int64_t ldl,

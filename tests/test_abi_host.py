@@ -219,3 +219,20 @@ def test_batch_graph_bad_arguments_rejected_on_host(nat):
     assert lib.cholmod_batch_graph_create(bad, 1, p(256), need, p(256), ctypes.byref(h)) == nat.ERR_ARG
     assert lib.cholmod_batch_graph_launch(None, None) == nat.ERR_ARG
     assert lib.cholmod_batch_graph_destroy(None) == nat.OK
+
+
+def test_noalloc_rejects_oversized_problems_on_host(nat):
+    """The allocation-free entry point refuses a problem whose workspace
+    exceeds its fixed device array before any HIP call (fake non-null
+    pointers: nothing is dereferenced)."""
+    lib = nat.load()
+    cap = lib.cholmod_noalloc_max_bytes()
+    assert cap >= 1 << 20
+    n, k = 60000, 16
+    assert nat.workspace_bytes(n, k) > cap
+    fake = ctypes.c_void_p(4096)
+    assert lib.cholmod_update_noalloc(fake, fake, n, k, n, 1, fake, None) == nat.ERR_ARG
+    # bad arguments as for the other entry points
+    assert lib.cholmod_update_noalloc(fake, fake, 10, 2, 5, 1, fake, None) == nat.ERR_ARG
+    assert lib.cholmod_update_noalloc(fake, fake, 10, 2, 10, 0, fake, None) == nat.ERR_ARG
+    assert lib.cholmod_update_noalloc(fake, fake, 10, 2, 10, 1, None, None) == nat.ERR_ARG
