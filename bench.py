@@ -72,6 +72,23 @@ def parse():
     return ap.parse_args()
 
 
+def host_cpu():
+    """(model name, cores available to this process) of the host."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count()
+    return model, avail
+
+
 def cpu_baseline(L, V, budget_s=10.0):
     """The oracle (serial C, one core) on the same workload: full-size
     update + downdate pairs, repeated until about budget_s seconds of CPU
@@ -90,9 +107,34 @@ def cpu_baseline(L, V, budget_s=10.0):
         dt = time.perf_counter() - t0
         if dt >= budget_s:
             break
+    model, avail = host_cpu()
     return {"value": mods / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "host_cores_available": avail,
             "sample": "%d full-size rank-%d modifications at n=%d (update + downdate pairs), "
                       "%.1f s on one host core" % (mods, V.shape[1], L.shape[0], dt)}
+
+
+def copy_bandwidth(dev, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (GB/s, bytes read + bytes written over the
+    time), the measured counterpart of the 8 TB/s peak: median of `reps`
+    copies of `nbytes` with HIP events."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    med = sorted(ts)[len(ts) // 2]
+    return 2.0 * nbytes / (med * 1e-3) / 1e9
 
 
 def batched(args):
@@ -524,6 +566,26 @@ def main():
         assert st == 0, (st, row, col)
     drift = float(torch.linalg.norm(torch.triu(L) - torch.triu(L0)) / torch.linalg.norm(L0))
 
+    # cold-MALL variant: 512 MB written between modifications (untimed)
+    # evicts the 100 MB factor from the 256 MB last-level cache, so each
+    # timed modification reads L from HBM
+    flush = torch.empty(64 << 20, dtype=torch.float64, device=dev)
+    cold = []
+    for s in range(min(K, 10)):
+        for sg, slot in ((1, 0), (-1, 1)):
+            flush.fill_(float(s))
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            chm.update_async(L, V, sg, stream=stream, workspace=ws, info=info[slot:slot + 1])
+            e1.record(stream)
+            e1.synchronize()
+            cold.append(e0.elapsed_time(e1))
+    del flush
+    torch.cuda.empty_cache()
+    cold_med = sorted(cold)[len(cold) // 2]
+    copy_gbs = copy_bandwidth(dev)
+
     per_sorted = sorted(per)
     med = per_sorted[len(per) // 2]
     mean = sum(per) / len(per)
@@ -555,9 +617,16 @@ def main():
         "rank1_equivalent_per_s": 2.0 * K * k / (total_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
+                     "measured_copy_GBps": copy_gbs,
+                     "frac_of_measured_copy": achieved / copy_gbs,
+                     "cold_mall": {"median_ms": cold_med,
+                                   "achieved_GBps": bytes_per_launch / (cold_med * 1e-3 / passes)
+                                   / 1e9,
+                                   "what": "512 MB written before each timed modification"},
                      "traffic": measured_traffic() if (n, k) == (5000, 16) else None,
                      "kernel": "k_sb_owner (one launch per 16-column pass)",
-                     "launches_per_modification": 1 + 2 * passes,
+                     "launches_per_modification": {"dominant_kernel": passes,
+                                                   "all": 1 + 2 * passes},
                      "avg_launch_us": avg_launch_us,
                      "alg_bytes_per_launch": bytes_per_launch},
         # the single-factor path is bound by its serial chain of blocks, not by

@@ -17,10 +17,10 @@ from paper_1011_1173_amd import inputs  # noqa: E402
 RESID_TOL = 1e-12
 
 
-def problem(n, k, seed, ldl=None, sigma=1):
-    """Seeded (L, V) as numpy arrays; for sigma = -1, L already contains V V^T
-    (the factor of A + V V^T, built by the oracle's own update), so the
-    downdate is well posed."""
+def problem(n, k, seed, ldl=None):
+    """Seeded (L, V) as numpy arrays (L = upper factor of G^T G + n I, V ~
+    N(0, 1)/sqrt(n)).  For a well-posed downdate by V, callers first add V V^T
+    with the oracle's own update."""
     L = inputs.spd_factor(n, seed, ldl=ldl).numpy()
     V = inputs.update_vectors(n, k, seed).numpy()
     return L, V
@@ -57,3 +57,20 @@ def rel_diff(a, b):
 
 def print_case(name, **kw):
     print("[case] %s %s" % (name, " ".join("%s=%s" % kv for kv in kw.items())), flush=True)
+
+
+def oracle_sequences(orc, starts, seqs, workers=8):
+    """Apply each factor's request sequence [(V, sigma), ...] to its starting
+    factor with the oracle, in order; factors run in parallel host threads
+    (the oracle releases the GIL).  Returns the final factors (numpy)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def run(args):
+        L, seq = args
+        for V, sg in seq:
+            L, st, _ = orc.modify(L, V, sg)
+            assert st == 0
+        return L
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(run, zip(starts, seqs)))

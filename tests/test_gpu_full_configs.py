@@ -4,19 +4,20 @@ to the oracle) bit for bit:
 
 * batched: 256 factors, n ~ U{64..4096}, k ~ U{1..32}, a mix of updates and
   downdates (a downdate removes a V added before, so A~ stays SPD), in FP64
-  and in FP32 storage, through one cholmod_update_batched call; a sample of
-  the FP64 factors is also checked against the oracle;
+  and in FP32 storage, through one cholmod_update_batched call; the four
+  smallest and four largest factors are also checked against the oracle;
 * served: a pool of 64 factors with n cycled over {1024, ..., 16384}, each
   receiving sliding-window request pairs (an update by a new V, then the
   downdate of the factor's oldest V) through the served mode; every factor
-  must end exactly as the same requests applied one at a time."""
+  must end exactly as the same requests applied one at a time, and every
+  factor with n <= 4096 as the oracle applies them (within 1e-12)."""
 import random
 
 import numpy as np
 import pytest
 import torch
 
-from gpu_util import RESID_TOL, inputs, print_case, rel_diff
+from gpu_util import RESID_TOL, inputs, oracle_sequences, print_case, rel_diff
 
 pytestmark = pytest.mark.gpu
 
@@ -56,14 +57,18 @@ def test_batched_256_uneven_equals_single(orc, f32):
     assert all(x[0] == 0 for x in stats), [x for x in stats if x[0] != 0][:4]
     for f in range(nf):
         assert torch.equal(single[f], batched[f]), "factor %d (n=%d)" % (f, ns[f])
-    if not f32:  # the three smallest factors against the oracle
-        for f in sorted(range(nf), key=lambda i: ns[i])[:3]:
-            ref, st, _ = orc.modify(L0[f].cpu().numpy(), Vs[f].cpu().numpy(), sg[f])
-            assert st == 0
-            assert rel_diff(batched[f].cpu().numpy(), ref) <= RESID_TOL
+    # the four smallest and the four largest factors against the oracle (FP64
+    # on the stored inputs; FP32 storage within 1e-5)
+    by_n = sorted(range(nf), key=lambda i: ns[i])
+    pick = by_n[:4] + by_n[-4:]
+    refs = oracle_sequences(orc, [L0[f].cpu().numpy().astype(np.float64) for f in pick],
+                            [[(Vs[f].cpu().numpy().astype(np.float64), sg[f])] for f in pick])
+    for f, ref in zip(pick, refs):
+        d = rel_diff(batched[f].cpu().numpy().astype(np.float64), ref)
+        assert d <= (1e-5 if f32 else RESID_TOL), (f, ns[f], d)
 
 
-def test_served_pool_equals_sequential():
+def test_served_pool_equals_sequential(orc):
     import paper_1011_1173_amd as chm
     sizes = [1024, 2048, 4096, 8192, 16384]
     nf = 64
@@ -99,3 +104,14 @@ def test_served_pool_equals_sequential():
     assert all(st == 0 for st, _ in res), [r for r in res if r[0] != 0][:4]
     for f in range(nf):
         assert torch.equal(ref[f], served[f]), "factor %d (n=%d)" % (f, ns[f])
+    # every factor with n <= 4096 against the oracle: the prior V, then its
+    # request pairs in order, from the generator's factor
+    small = [f for f in range(nf) if ns[f] <= 4096]
+    starts = [inputs.spd_factor(ns[f], 8000 + f % len(sizes), device="cuda").cpu().numpy()
+              for f in small]
+    seqs = [[(prior[f].cpu().numpy(), +1)] + [(V.cpu().numpy(), s) for ff, V, s in reqs if ff == f]
+            for f in small]
+    refs = oracle_sequences(orc, starts, seqs)
+    for f, r in zip(small, refs):
+        d = rel_diff(served[f].cpu().numpy(), r)
+        assert d <= RESID_TOL, (f, ns[f], d)

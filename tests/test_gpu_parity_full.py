@@ -1,0 +1,133 @@
+"""Element-by-element parity of the fast path -- the schedule the benchmark
+times -- with the oracle, at full sizes (needs an MI355X).
+
+For every element of the upper triangle the difference from the oracle's
+factor, over the largest oracle element, must stay within ELEM_TOL; the
+relative Frobenius distance and the relative residual must stay within the
+FP64 bound (1e-12).  ELEM_TOL follows from the fast evaluation (rsqrt with
+two Newton steps, multiplication by 1/c, fused multiply-adds): each rotation
+differs from the IEEE statements by a few ulps (<= 4 * 2^-53 relative), an
+element of L~ depends on at most n*k earlier rotations through V, and
+independent rounding errors add in quadrature, so its deviation relative to
+its row's scale is of order 4 * 2^-53 * sqrt(n k) ~ 2.5e-13 at n = 5000,
+k = 64; off-diagonal elements are ~1/100 of the largest (diagonal) element
+for this input recipe, which leaves the normalised maximum near 1e-15 --
+ELEM_TOL = 1e-13 keeps two orders of magnitude of margin and still catches a
+localised error far below what the Frobenius norm would show.
+
+Cases: n = 5000 (the headline shape) with k in {1, 16, 64} and sigma = +-1;
+n = 17000, k = 16 (266 blocks of 64 rows: more blocks than compute units,
+the late-owner regime), the whole factor; and the exact evaluation mode at
+n = 5000, k = 16 bit for bit.  The downdate cases downdate the oracle's
+updated factor, so the inputs never come from the GPU path.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import RESID_TOL, inputs, print_case, rel_diff
+
+pytestmark = pytest.mark.gpu
+ELEM_TOL = 1e-13
+
+_cache = {}
+
+
+def elem_err(out, ref):
+    """max_ij |out - ref| / max_ij |ref| over the upper triangle."""
+    n = ref.shape[0]
+    a = np.triu(out[:, :n])
+    b = np.triu(ref[:, :n])
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def residual_gpu(Lnew, L, V, sigma):
+    """||U~^T U~ - (U^T U + sigma V V^T)||_F / ||.||_F, library FP64 GEMMs on the GPU."""
+    n = L.shape[0]
+    U = torch.triu(torch.from_numpy(np.ascontiguousarray(L[:, :n])).cuda())
+    At = U.T.contiguous() @ U
+    del U
+    Vt = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    At += sigma * (Vt @ Vt.T.contiguous())
+    Un = torch.triu(torch.from_numpy(np.ascontiguousarray(Lnew[:, :n])).cuda())
+    R = Un.T.contiguous() @ Un
+    del Un
+    R -= At
+    r = float(torch.linalg.norm(R) / torch.linalg.norm(At))
+    del R, At
+    torch.cuda.empty_cache()
+    return r
+
+
+def oracle_pair(orc, n, k, seed):
+    """(L, V, oracle update of L, oracle downdate of that) for one shape."""
+    key = (n, k, seed)
+    if key not in _cache:
+        if n > 6000:  # 2.3 GB per matrix: keep only this shape
+            _cache.clear()
+        dev = "cuda" if n > 6000 else "cpu"  # G^T G of the generator on the GPU when large
+        L = inputs.spd_factor(n, seed, device=dev).cpu().numpy()
+        V = inputs.update_vectors(n, k, seed).numpy()
+        up, st, _ = orc.modify(L, V, +1)
+        assert st == 0
+        down, st, _ = orc.modify(up, V, -1)
+        assert st == 0
+        _cache[key] = (L, V, up, down)
+    return _cache[key]
+
+
+def run_fast(L, V, sigma, **kw):
+    import paper_1011_1173_amd as chm
+    Ld = torch.from_numpy(np.ascontiguousarray(L)).cuda()
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    st, row, col = chm.update_async(Ld, Vd, sigma, **kw).status()
+    assert st == 0, (st, row, col)
+    out = Ld.cpu().numpy()
+    del Ld, Vd
+    return out
+
+
+def check(out, ref, Lin, V, sigma, resid=True):
+    e = elem_err(out, ref)
+    d = rel_diff(out, ref)
+    print("  elementwise %.3e  frobenius %.3e" % (e, d), flush=True)
+    assert np.all(np.diag(out) > 0)
+    assert e <= ELEM_TOL, e
+    assert d <= RESID_TOL, d
+    if resid:
+        r = residual_gpu(out, Lin, V, sigma)
+        print("  residual %.3e" % r, flush=True)
+        assert r <= RESID_TOL, r
+
+
+@pytest.mark.parametrize("k", [1, 16, 64])
+@pytest.mark.parametrize("sigma", [1, -1])
+def test_fast_path_elementwise_headline_shape(orc, k, sigma):
+    n = 5000
+    print_case("fast-elementwise", n=n, k=k, sigma=sigma)
+    L, V, up, down = oracle_pair(orc, n, k, seed=2)
+    if sigma > 0:
+        check(run_fast(L, V, +1), up, L, V, +1)
+    else:
+        check(run_fast(up, V, -1), down, up, V, -1)
+
+
+@pytest.mark.parametrize("sigma", [1, -1])
+def test_fast_path_elementwise_more_blocks_than_compute_units(orc, sigma):
+    n, k = 17000, 16
+    print_case("fast-elementwise-late-owners", n=n, k=k, sigma=sigma)
+    L, V, up, down = oracle_pair(orc, n, k, seed=63)
+    if sigma > 0:
+        check(run_fast(L, V, +1), up, L, V, +1)
+    else:
+        check(run_fast(up, V, -1), down, up, V, -1)
+
+
+def test_exact_mode_bitwise_headline_shape(orc):
+    n, k = 5000, 16
+    print_case("exact-bitwise", n=n, k=k)
+    L, V, up, down = oracle_pair(orc, n, k, seed=2)
+    out = run_fast(L, V, +1, exact=True)
+    assert np.array_equal(out, up), "max |diff| = %g" % np.abs(out - up).max()
+    back = run_fast(up, V, -1, exact=True)
+    assert np.array_equal(back, down), "max |diff| = %g" % np.abs(back - down).max()

@@ -1,11 +1,12 @@
 """Served mode (cholmod_server_*): results equal the same requests applied
-one at a time through the single-factor entry points, bit for bit; failures
-and oversized requests are reported per request."""
+one at a time through the single-factor entry points, bit for bit, and the
+oracle's results within the FP64 (1e-12) or FP32-storage (1e-5) bound;
+failures and oversized requests are reported per request."""
 import numpy as np
 import pytest
 import torch
 
-from gpu_util import print_case, problem
+from gpu_util import RESID_TOL, oracle_sequences, print_case, problem, rel_diff
 
 pytestmark = pytest.mark.gpu
 
@@ -14,7 +15,7 @@ def dev(a, f32):
     return torch.from_numpy(np.ascontiguousarray(a.astype(np.float32 if f32 else np.float64))).cuda()
 
 
-def test_server_equals_sequential():
+def test_server_equals_sequential(orc):
     import paper_1011_1173_amd as chm
     rng = np.random.default_rng(11)
     shapes = [(300, False), (129, True), (64, False), (1000, False), (77, True)]
@@ -49,6 +50,17 @@ def test_server_equals_sequential():
         a = ref[f].cpu().numpy()
         b = Ls[f].cpu().numpy()
         assert np.array_equal(a, b), "factor %d" % f
+    # and against the oracle: the same requests in FP64 on the stored inputs
+    # (FP32-storage factors: their binary32 values), bound 1e-12 / 1e-5
+    starts, seqs = [], []
+    for f, (b, (n, f32)) in enumerate(zip(base, shapes)):
+        cast = (lambda a: a.astype(np.float32).astype(np.float64)) if f32 else (lambda a: a)
+        starts.append(cast(b))
+        seqs.append([(cast(V), sg) for ff, V, sg in reqs if ff == f])
+    refs = oracle_sequences(orc, starts, seqs)
+    for f, (n, f32) in enumerate(shapes):
+        d = rel_diff(Ls[f].cpu().numpy().astype(np.float64), refs[f])
+        assert d <= (1e-5 if f32 else RESID_TOL), (f, n, f32, d)
 
 
 def test_server_reports_failures_per_request(orc):
