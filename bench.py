@@ -45,6 +45,31 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
+def critical_path(chm, n, k, passes, mean_ms, alg_bytes):
+    """The serial floor of one factor: the rows form a chain (a row's Compute
+    needs V after the Apply of every earlier row), run block by block.  The
+    library's latency probe measures a 64-row block's chain alone (in LDS)
+    and the hand-off between workgroups; T_crit = blocks x passes x (chain
+    of a block), which no schedule of this blocking can beat, against the
+    HBM time of the algorithmic bytes."""
+    nb = ((n + 63) // 64) * passes
+    out = {"blocks_x_passes": nb, "us_per_block": mean_ms * 1e3 / nb}
+    try:
+        step_ns, block_ns, hand_x_ns, hand_s_ns = chm._native.probe_latency(
+            k=min(k, 16), blocks=200, rounds=2000)
+    except RuntimeError as e:
+        out["probe_error"] = str(e)
+        return out
+    t_crit_ms = nb * block_ns * 1e-6
+    t_hbm_ms = alg_bytes / (HBM_PEAK_GBS * 1e9) * 1e3
+    out.update({"chain_step_ns": step_ns, "lambda_row_ns": block_ns / 64.0,
+                "chain_ns_per_block": block_ns, "handoff_ns_cross_xcd": hand_x_ns,
+                "handoff_ns_same_xcd": hand_s_ns, "t_crit_ms": t_crit_ms,
+                "t_hbm_ms": t_hbm_ms, "max_hbm_frac_at_t_crit": t_hbm_ms / t_crit_ms,
+                "measured_over_t_crit": mean_ms / t_crit_ms})
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -632,8 +657,7 @@ def main():
         # the single-factor path is bound by its serial chain of blocks, not by
         # HBM: the time per 64-row block (and 16-column pass) is the figure to
         # compare between versions
-        "critical_path": {"blocks_x_passes": ((n + 63) // 64) * passes,
-                          "us_per_block": mean * 1e3 / (((n + 63) // 64) * passes)},
+        "critical_path": critical_path(chm, n, k, passes, mean, alg_bytes),
         "round_trip_drift": drift,
         "wall_s": wall,
     }

@@ -273,21 +273,37 @@ int cholmod_update_ooc(void *L_host, const void *V, int64_t n, int64_t k, int64_
 /*
  * Served mode: factors registered once, then a stream of requests (one
  * update or downdate of one factor by a caller-owned V) batched
- * continuously onto one GPU by a library worker thread.  Requests of one
- * factor run in submission order; requests of different factors run
- * concurrently in batches (cholmod_update_batched's schedule, so each
- * result is bit for bit the single-factor result).  The server owns one
- * non-blocking stream on cfg->device, two batch slots of cfg->ws_bytes
- * device workspace each (its HBM budget besides the factors), and pinned
- * staging memory; all are allocated by cholmod_server_create.
+ * continuously onto one GPU by a library worker thread.
+ *   Admission by HBM footprint: the server owns a device arena of
+ *   cfg->ws_bytes bytes (its HBM budget besides the factors); a waiting
+ *   request joins the next batch when its workspace (cholmod_workspace_bytes
+ *   of its n, k and storage type, plus a few hundred bytes of tables) fits
+ *   into the arena's free part.  A request that cannot fit into the whole
+ *   arena fails with CHOLMOD_ERR_ARG.
+ *   Overlap: up to cfg->streams batches are in flight at once, each on its
+ *   own non-blocking stream; a batch formed while others run is launched at
+ *   once and shares the GPU with them.
+ *   Order: requests of one factor run in submission order (a factor's next
+ *   request waits for the previous one); requests of different factors run
+ *   concurrently, oldest first.  Each batch is cholmod_update_batched's
+ *   schedule, so each result is bit for bit the single-factor result.
+ *   Completion: a request completes as soon as its factor is finished in
+ *   its batch (the device writes the factor's status into host-mapped
+ *   memory), not when the whole batch ends.
+ * The arena, streams and pinned memory are allocated by
+ * cholmod_server_create.
  */
 typedef struct cholmod_server cholmod_server;
 
 typedef struct cholmod_server_cfg {
-  size_t ws_bytes;    /* device workspace per batch slot (>= 4096); a batch takes
-                         as many waiting requests as fit (cholmod_workspace_bytes_batched) */
+  size_t ws_bytes;    /* HBM budget of the work in flight (>= 4096): one device
+                         arena that the batches in flight share; a request is
+                         admitted when its workspace fits into the free part */
   int32_t max_batch;  /* most requests per batch (0 = 256, at most 65535) */
   int32_t device;     /* HIP device of the factors */
+  int32_t streams;    /* batches in flight at once, each on its own stream
+                         (0 = 4, at most 16) */
+  int32_t reserved;   /* 0 */
 } cholmod_server_cfg;
 
 /* Create a server and start its worker.  CHOLMOD_ERR_ARG for a bad cfg. */
@@ -328,6 +344,26 @@ int cholmod_server_drain(cholmod_server *srv);
 
 /* Drain, stop the worker and free the server's resources. */
 int cholmod_server_destroy(cholmod_server *srv);
+
+/*
+ * Measurement entry point (not part of a modification): the two latencies
+ * that bound the time of one factor, whose rows form a serial chain
+ * (Algorithm 1: row i's Compute needs V_i after the Apply of rows < i).
+ *   out4[0]  ns per step of the chain of a 64-row block with k columns of V
+ *            (one step: Compute of one row for every column, the Apply of
+ *            two rows to the next column, one workgroup barrier); a block
+ *            takes 64 + k - 1 steps
+ *   out4[1]  ns per 64-row block's chain
+ *   out4[2]  ns per one-way hand-off of a flag between workgroups on two
+ *            different XCDs (device-scope store, polling device-scope load)
+ *   out4[3]  the same between two workgroups on one XCD
+ * k in 1..16; `blocks` chains (1..100000) and `rounds` round trips
+ * (1..1000000) are averaged.  Runs synthetic inputs held in LDS, allocates
+ * 4 KB of device memory for the call, and waits for `stream`.  Returns
+ * CHOLMOD_OK, CHOLMOD_ERR_ARG, or CHOLMOD_ERR_HIP (also if a bounded wait
+ * of the hand-off ran out).
+ */
+int cholmod_probe_latency(int k, int blocks, int rounds, double *out4, cholmod_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -318,12 +318,15 @@ class BatchGraph:
 
 class Server:
     """Served mode (cholmod_server_*): registered factors, submitted requests,
-    continuous batching by a library worker thread.  The Python object keeps
-    every registered factor and every pending V alive."""
+    continuous batching by a library worker thread: admission by the HBM
+    budget ``ws_bytes``, up to ``streams`` batches in flight at once, a
+    request complete as soon as its factor is.  The Python object keeps every
+    registered factor and every pending V alive."""
 
-    def __init__(self, ws_bytes: int = 1 << 30, max_batch: int = 256, device=None):
+    def __init__(self, ws_bytes: int = 1 << 30, max_batch: int = 256, device=None,
+                 streams: int = 4):
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        cfg = _native.ServerCfg(int(ws_bytes), int(max_batch), int(dev.index))
+        cfg = _native.ServerCfg(int(ws_bytes), int(max_batch), int(dev.index), int(streams), 0)
         h = ctypes.c_void_p()
         _raise_for(_native.load().cholmod_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h, self.device = h, dev

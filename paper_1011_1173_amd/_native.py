@@ -26,14 +26,15 @@ EXPORTS = (
     "cholmod_batch_graph_create", "cholmod_batch_graph_launch", "cholmod_batch_graph_destroy",
     "cholmod_server_create", "cholmod_server_add_factor", "cholmod_server_submit",
     "cholmod_server_poll", "cholmod_server_drain", "cholmod_server_destroy",
-    "cholmod_noalloc_max_bytes", "cholmod_update_noalloc",
+    "cholmod_noalloc_max_bytes", "cholmod_update_noalloc", "cholmod_probe_latency",
 )
 
 
 class ServerCfg(ctypes.Structure):
     """struct cholmod_server_cfg of the header."""
     _fields_ = [("ws_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int32),
-                ("device", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("streams", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Desc(ctypes.Structure):
@@ -77,6 +78,8 @@ def load():
     lib.cholmod_noalloc_max_bytes.restype = sz
     lib.cholmod_update_noalloc.argtypes = [p, p, i64, i64, i64, ci, p, p]
     lib.cholmod_update_noalloc.restype = ci
+    lib.cholmod_probe_latency.argtypes = [ci, ci, ci, ctypes.POINTER(ctypes.c_double), p]
+    lib.cholmod_probe_latency.restype = ci
     lib.cholmod_update_f32s.argtypes = [p, p, i64, i64, i64, ci, p]
     lib.cholmod_update_f32s.restype = ci
     lib.cholmod_update_f32s_async.argtypes = [p, p, i64, i64, i64, ci, p, sz, p, p]
@@ -127,3 +130,13 @@ def decode_info(info: int, k: int):
 
 def workspace_bytes(n: int, k: int, dtype: int = F64) -> int:
     return int(load().cholmod_workspace_bytes(int(n), int(k), int(dtype)))
+
+
+def probe_latency(k: int = 16, blocks: int = 200, rounds: int = 2000, stream=None):
+    """cholmod_probe_latency: (ns per chain step, ns per 64-row block's chain,
+    ns per hand-off across XCDs, ns per hand-off within one XCD)."""
+    out = (ctypes.c_double * 4)()
+    st = load().cholmod_probe_latency(int(k), int(blocks), int(rounds), out, stream)
+    if st != OK:
+        raise RuntimeError("cholmod_probe_latency: %s" % status_string(st))
+    return tuple(out)

@@ -29,8 +29,12 @@ hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, floa
 hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
                             const BatchEntry* d_ent, const BatchStep* steps, int64_t nsteps);
 hipError_t run_sysblk_batch_prepare(hipStream_t st, const BatchFactor* d_fac, int64_t count);
+hipError_t run_probe_latency(hipStream_t st, int kc, int blocks, int rounds, double* out4,
+                             int* timed_out);
 hipError_t run_sysblk_batch_step(hipStream_t st, const BatchFactor* d_fac,
                                  const BatchEntry* d_ent, const BatchStep& S);
+hipError_t run_sysblk_qbatch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
+                             const QItem* d_items, int64_t nitems, int32_t* d_ticket);
 
 namespace {
 
@@ -42,9 +46,10 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // Workspace layout (all offsets 256-byte aligned):
 //   [0, 768)         control words: the first failing row (int64) at 0
 //   W                n*k private copy of V
-//   T                n*max(16, min(k, 64)) rotation records of 32 bytes
-//   F                one int32 per 16-column pass: the ticket counter of
-//                    that pass's launch in the fast schedule
+//   T                n*16*ceil(k/16) rotation records of 32 bytes (16 per row
+//                    for each 16-column pass of the fast schedule)
+//   F                int32 ticket counters (the first one is the fast
+//                    schedule's work counter)
 struct WsLayout {
   size_t ctrl = 0, w = 0, t = 0, f = 0, total = 0;
   int64_t nflags = 0;
@@ -62,7 +67,9 @@ bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out) {
   L.ctrl = 0;
   L.w = 3 * kAlign;  // control words
   L.t = L.w + align_up((size_t)(n * k) * es);
-  int64_t kp = k < kKPass ? k : kKPass;
+  // records: 16 per row for every 16-column pass (the fast schedule), which
+  // also covers the blocked schedule's min(k, 64) per row
+  int64_t kp = (k + 15) / 16 * 16;
   if (kp < 16) kp = 16;
   L.f = L.t + align_up((size_t)(n * kp) * sizeof(Coef));
   L.nflags = (k + 15) / 16;
@@ -241,11 +248,18 @@ void* scratch_address(int dev) {
 // ------------------------------------------------------------------ batched
 constexpr int64_t kBlock = 64, kPass = 16, kMaxBatch = 65535;
 
+// Two forms of a batch.  Queued (the batched entry points): the factors'
+// owner items in one table, taken by one persistent launch from a work
+// counter; the tables are [factors][items][counter].  Stepped (the
+// out-of-core form): one launch per block step; the tables are
+// [factors][entries].
 struct BatchPlan {
+  bool queued = true;
   std::vector<BatchFactor> fac;
   std::vector<BatchEntry> ent;
   std::vector<BatchStep> steps;
-  size_t off_ent = 0, off_fac_data = 0, table_bytes = 0, total = 0;
+  std::vector<QItem> items;
+  size_t off_ent = 0, off_items = 0, off_ticket = 0, off_left = 0, table_bytes = 0, total = 0;
   std::vector<size_t> off_ctrl, off_w, off_t;
 };
 
@@ -257,23 +271,36 @@ int validate_desc(const cholmod_desc& d) {
 }
 
 // Sizes and (when ws != nullptr) device pointers of a batch; the schedule
-// of each factor is the single-factor one (64-row blocks, 16-column passes).
-int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P) {
+// of each factor is the single-factor one (64-row blocks, 16-column passes,
+// the same operations in the same order), so every factor's result is the
+// one it gets alone.
+int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P,
+               bool queued = true) {
   if (count < 0 || count > kMaxBatch) return CHOLMOD_ERR_ARG;
   if (count > 0 && descs == nullptr) return CHOLMOD_ERR_ARG;
+  P->queued = queued;
   std::vector<int64_t> steps(count), blocks(count);
-  int64_t total_ent = 0, smax = 0;
+  int64_t total_ent = 0, total_items = 0, smax = 0, bmax = 0;
   for (int64_t f = 0; f < count; ++f) {
     const int v = validate_desc(descs[f]);
     if (v) return v;
     const cholmod_desc& d = descs[f];
-    blocks[f] = ceil_div(d.n, kBlock);
-    steps[f] = (d.n == 0 || d.k == 0) ? 0 : blocks[f] * ceil_div(d.k, kPass);
+    blocks[f] = (d.n == 0 || d.k == 0) ? 0 : ceil_div(d.n, kBlock);
+    steps[f] = blocks[f] * ceil_div(d.k, kPass);
     total_ent += steps[f];
+    total_items += blocks[f];
     smax = std::max(smax, steps[f]);
+    bmax = std::max(bmax, blocks[f]);
   }
-  P->off_ent = align_up((size_t)count * sizeof(BatchFactor));
-  P->table_bytes = P->off_ent + align_up((size_t)total_ent * sizeof(BatchEntry));
+  if (total_items > INT32_MAX) return CHOLMOD_ERR_ARG;
+  P->off_ent = P->off_items = align_up((size_t)count * sizeof(BatchFactor));
+  if (queued) {
+    P->off_ticket = P->off_items + align_up((size_t)total_items * sizeof(QItem));
+    P->off_left = P->off_ticket + kAlign;
+    P->table_bytes = P->off_left + align_up((size_t)count * sizeof(int32_t));
+  } else {
+    P->table_bytes = P->off_ent + align_up((size_t)total_ent * sizeof(BatchEntry));
+  }
   size_t off = P->table_bytes;
   P->off_ctrl.resize(count);
   P->off_w.resize(count);
@@ -300,6 +327,8 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P)
     F.T = ws + P->off_t[f];
     F.info = nullptr;  // set by the caller
     F.stop = (int64_t*)(ws + P->off_ctrl[f]);
+    F.left = queued ? (int32_t*)(ws + P->off_left) + f : nullptr;
+    F.done = nullptr;  // set by a caller that wants per-factor completion
     F.n = d.n;
     F.k = d.k;
     F.ldl = d.ldl;
@@ -311,6 +340,21 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P)
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int64_t a, int64_t b) { return steps[a] > steps[b]; });
+  if (queued) {
+    // by block index, longest factor first within a block index: an item
+    // waits only for its factor's items of lower blocks, which come earlier
+    P->items.clear();
+    P->items.reserve(total_items);
+    for (int64_t b = 0; b < bmax; ++b)
+      for (int64_t f : order) {
+        if (b >= blocks[f]) continue;
+        QItem it;
+        it.f = (int32_t)f;
+        it.j = (int32_t)b;
+        P->items.push_back(it);
+      }
+    return CHOLMOD_OK;
+  }
   P->ent.clear();
   P->ent.reserve(total_ent);
   P->steps.assign(smax, BatchStep{});
@@ -344,22 +388,38 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P)
 
 }  // namespace
 
-size_t batch_table_bytes(const cholmod_desc* descs, int64_t count) {
+size_t batch_table_bytes(const cholmod_desc* descs, int64_t count, bool queued) {
   BatchPlan P;
-  if (plan_batch(descs, count, nullptr, &P) != CHOLMOD_OK) return 0;
+  if (plan_batch(descs, count, nullptr, &P, queued) != CHOLMOD_OK) return 0;
   return P.table_bytes;
 }
 
-size_t batch_workspace_bytes(const cholmod_desc* descs, int64_t count) {
+size_t batch_workspace_bytes(const cholmod_desc* descs, int64_t count, bool queued) {
   BatchPlan P;
-  if (plan_batch(descs, count, nullptr, &P) != CHOLMOD_OK) return 0;
+  if (plan_batch(descs, count, nullptr, &P, queued) != CHOLMOD_OK) return 0;
   return P.total;
 }
 
 // The batch tables of plan P (built for workspace ws) in host memory at h.
 void write_tables(const BatchPlan& P, char* h) {
   std::memcpy(h, P.fac.data(), P.fac.size() * sizeof(BatchFactor));
-  if (!P.ent.empty()) std::memcpy(h + P.off_ent, P.ent.data(), P.ent.size() * sizeof(BatchEntry));
+  if (P.queued) {
+    if (!P.items.empty())
+      std::memcpy(h + P.off_items, P.items.data(), P.items.size() * sizeof(QItem));
+    std::memset(h + P.off_ticket, 0, kAlign);
+  } else if (!P.ent.empty()) {
+    std::memcpy(h + P.off_ent, P.ent.data(), P.ent.size() * sizeof(BatchEntry));
+  }
+}
+
+// The launches of a planned batch on `st` (tables already in ws).
+hipError_t run_planned(hipStream_t st, const BatchPlan& P, char* ws, int64_t count) {
+  const BatchFactor* d_fac = (const BatchFactor*)ws;
+  if (P.queued)
+    return run_sysblk_qbatch(st, d_fac, count, (const QItem*)(ws + P.off_items),
+                             (int64_t)P.items.size(), (int32_t*)(ws + P.off_ticket));
+  return run_sysblk_batch(st, d_fac, count, (const BatchEntry*)(ws + P.off_ent), P.steps.data(),
+                          (int64_t)P.steps.size());
 }
 
 int64_t batch_steps_of(const cholmod_desc& d) {
@@ -368,18 +428,22 @@ int64_t batch_steps_of(const cholmod_desc& d) {
 
 int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_bytes,
                   int64_t* d_info, hipStream_t st, void* stage, size_t stage_bytes,
-                  const std::function<int(int64_t)>* after_step) {
+                  const std::function<int(int64_t)>* after_step, int64_t* d_done) {
   BatchPlan P;
-  int rc = plan_batch(descs, count, nullptr, &P);
+  const bool queued = after_step == nullptr;
+  int rc = plan_batch(descs, count, nullptr, &P, queued);
   if (rc) return rc;
   if (count == 0) return CHOLMOD_OK;
   if (d_info == nullptr || ((uintptr_t)d_info & 7u) != 0) return CHOLMOD_ERR_ARG;
   if (ws == nullptr || ws_bytes < P.total || ((uintptr_t)ws % kAlign) != 0)
     return CHOLMOD_ERR_ARG;
   if (stage == nullptr || stage_bytes < P.table_bytes) return CHOLMOD_ERR_ARG;
-  rc = plan_batch(descs, count, (char*)ws, &P);
+  rc = plan_batch(descs, count, (char*)ws, &P, queued);
   if (rc) return rc;
-  for (int64_t f = 0; f < count; ++f) P.fac[f].info = d_info + f;
+  for (int64_t f = 0; f < count; ++f) {
+    P.fac[f].info = d_info + f;
+    if (queued && d_done) P.fac[f].done = d_done + f;
+  }
   char* h = (char*)stage;
   write_tables(P, h);
   if (hipMemcpyAsync(ws, h, P.table_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
@@ -387,8 +451,7 @@ int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_
   const BatchFactor* d_fac = (const BatchFactor*)ws;
   const BatchEntry* d_ent = (const BatchEntry*)((char*)ws + P.off_ent);
   if (after_step == nullptr) {
-    hipError_t e = run_sysblk_batch(st, d_fac, count, d_ent, P.steps.data(),
-                                    (int64_t)P.steps.size());
+    hipError_t e = run_planned(st, P, (char*)ws, count);
     return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
   }
   if (run_sysblk_batch_prepare(st, d_fac, count) != hipSuccess) return CHOLMOD_ERR_HIP;
@@ -436,7 +499,7 @@ bool ooc_layout(int64_t n, int64_t k, int dtype, OocLayout* out) {
   if (n < 0 || k < 0 || (dtype != CHOLMOD_F64 && dtype != CHOLMOD_F32S)) return false;
   // non-null placeholders: sizing does not look at the pointers
   const cholmod_desc d = ooc_desc((void*)kAlign, (const void*)kAlign, n, k, 1, dtype);
-  const size_t batch = batch_workspace_bytes(&d, 1);
+  const size_t batch = batch_workspace_bytes(&d, 1, false);
   if (batch == 0) return false;
   const size_t es = dtype == CHOLMOD_F64 ? 8 : 4;
   if (!mul_ok(kBlock * (int64_t)es, n > 1 ? n : 1, INT64_MAX / 8)) return false;
@@ -555,7 +618,7 @@ int update_ooc(void* L_host, const void* V, int64_t n, int64_t k, int64_t ldl, i
   int64_t host_info = CHOLMOD_INFO_NONE;
   do {
     BatchPlan P;
-    rc = plan_batch(&d, 1, (char*)ws, &P);
+    rc = plan_batch(&d, 1, (char*)ws, &P, false);
     if (rc) break;
     char* base = (char*)ws;
     int64_t* d_info = (int64_t*)(base + lay.info);
@@ -806,6 +869,16 @@ int cholmod_update(double* L, const double* V, int64_t n, int64_t k, int64_t ldl
                   });
 }
 
+int cholmod_probe_latency(int k, int blocks, int rounds, double* out4, cholmod_stream_t stream) {
+  if (k < 1 || k > 16 || blocks < 1 || blocks > 100000 || rounds < 1 || rounds > 1000000 ||
+      out4 == nullptr)
+    return CHOLMOD_ERR_ARG;
+  int timed_out = 0;
+  if (run_probe_latency((hipStream_t)stream, k, blocks, rounds, out4, &timed_out) != hipSuccess)
+    return CHOLMOD_ERR_HIP;
+  return timed_out ? CHOLMOD_ERR_HIP : CHOLMOD_OK;
+}
+
 size_t cholmod_noalloc_max_bytes(void) { return kScratchBytes; }
 
 int cholmod_update_noalloc(double* L, const double* V, int64_t n, int64_t k, int64_t ldl,
@@ -881,9 +954,7 @@ int cholmod_batch_graph_create(const cholmod_desc* descs, int64_t count, void* w
   rc = CHOLMOD_ERR_HIP;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess) {
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-      const hipError_t e = run_sysblk_batch(cs, (const BatchFactor*)ws, count,
-                                            (const BatchEntry*)((char*)ws + P.off_ent),
-                                            P.steps.data(), (int64_t)P.steps.size());
+      const hipError_t e = run_planned(cs, P, (char*)ws, count);
       const hipError_t ee = hipStreamEndCapture(cs, &graph);
       if (e == hipSuccess && ee == hipSuccess && graph != nullptr &&
           hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess)

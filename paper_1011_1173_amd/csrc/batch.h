@@ -12,9 +12,12 @@ struct BatchFactor {
   void* L;         // caller's factor
   const void* V;   // caller's V (read by the preparation launch only)
   void* W;         // private copy of V in the workspace
-  void* T;         // rotation records, n x 16 slots of 32 bytes
+  void* T;         // rotation records, n x 16 slots of 32 bytes per 16-column pass
   int64_t* info;   // caller's info word for this factor
   int64_t* stop;   // first failing row
+  int32_t* left;   // queued form: the factor's owner items not yet finished
+  int64_t* done;   // queued form, or null: where the last item to finish
+                   // writes the factor's info word (host-mapped memory)
   int64_t n, k, ldl;
   int32_t sigma, dtype;
 };
@@ -34,6 +37,13 @@ struct BatchEntry {
   int32_t kc;      // columns of V in this pass
   int32_t rest0;   // index of the entry's first rest workgroup among the step's
                    // (a rest workgroup applies two 64-column tiles)
+};
+
+// One owner item of a queued batch: the columns of block j of factor f,
+// every pass (device table, in the order the workgroups take them).
+struct QItem {
+  int32_t f;
+  int32_t j;
 };
 
 // Host-side description of one launch.

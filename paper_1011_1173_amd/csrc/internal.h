@@ -10,9 +10,11 @@
 namespace chm {
 
 // Bytes of the batch tables (uploaded at the start of the workspace) and of
-// the whole batch workspace; 0 if any descriptor is invalid.
-size_t batch_table_bytes(const cholmod_desc* descs, int64_t count);
-size_t batch_workspace_bytes(const cholmod_desc* descs, int64_t count);
+// the whole batch workspace; 0 if any descriptor is invalid.  queued: the
+// one-launch form of the batched entry points; otherwise the form with one
+// launch per block step (out-of-core, and enqueue_batch with after_step).
+size_t batch_table_bytes(const cholmod_desc* descs, int64_t count, bool queued = true);
+size_t batch_workspace_bytes(const cholmod_desc* descs, int64_t count, bool queued = true);
 
 // Launches of a factor in a batch: its step s runs in the batch's launch s,
 // for s < batch_steps_of(desc); after the launch of its last step the
@@ -21,12 +23,16 @@ int64_t batch_steps_of(const cholmod_desc& d);
 
 // Validate, build the tables in the pinned host buffer `stage` (at least
 // batch_table_bytes), upload them to `ws` and enqueue the batch on `st`.
-// The caller keeps `stage` unchanged until the upload has run.  With
-// after_step, it is called after the launch of every step s is enqueued (to
-// enqueue more work behind it on `st`); a non-zero return stops and is
-// returned.
+// The caller keeps `stage` unchanged until the upload has run.  Without
+// after_step the batch is the queued form (one persistent launch); d_done
+// (device addresses of `count` int64 words, or null) then receives each
+// factor's info word as soon as the factor is finished.  With after_step the
+// batch runs one launch per block step and after_step is called after the
+// launch of every step s is enqueued (to enqueue more work behind it on
+// `st`); a non-zero return stops and is returned.
 int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_bytes,
                   int64_t* d_info, hipStream_t st, void* stage, size_t stage_bytes,
-                  const std::function<int(int64_t)>* after_step = nullptr);
+                  const std::function<int(int64_t)>* after_step = nullptr,
+                  int64_t* d_done = nullptr);
 
 }  // namespace chm

@@ -14,8 +14,8 @@
 //   * the radicand of column m is carried from column m-1: with
 //     t_{m-1} = L_ii^2 as it stood before column m, t_m = t_{m-1} + sigma V^2
 //     in one fused multiply-add (for m = 0, t_{-1} = L_ii * L_ii);
-//   * y = 1/sqrt(t_m) from the hardware reciprocal square root refined by two
-//     Newton steps; then w = t y, c = w / L_ii = w * (1/L_ii),
+//   * y = 1/sqrt(t_m) from the hardware reciprocal square root refined by one
+//     third-order step (rsqrt_refined); then w = t y, c = w / L_ii = w * (1/L_ii),
 //     s = V / L_ii = V * (1/L_ii), and 1/c = L_ii * y; the next column uses
 //     L_ii <- w and 1/L_ii <- y;
 //   * Apply multiplies by 1/c and uses fused multiply-adds, keeping the new
@@ -62,15 +62,19 @@ __device__ __forceinline__ void apply_exact(const Coef& k, double sg, double& li
 }
 
 // ---------------------------------------------------------------- FAST
+// 1/sqrt(t): the hardware estimate y0 (relative error about 2^-24) refined by
+// one third-order step.  With e = 1 - t y0^2, the exact value is
+// y0 (1 - e)^(-1/2) = y0 (1 + e/2 + 3 e^2/8 + O(e^3)); the O(e^3) term is
+// below 2^-70, so y = y0 + (y0 e) (1/2 + 3 e/8) is within about one ulp --
+// as accurate as two Newton steps, in 5 dependent-light operations instead
+// of 8.
 __device__ __forceinline__ double rsqrt_refined(double t) {
-  double y = __builtin_amdgcn_rsq(t);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double r = t * y;
-    const double e = __builtin_fma(-r, y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-  }
-  return y;
+  const double y0 = __builtin_amdgcn_rsq(t);
+  const double r = t * y0;
+  const double e = __builtin_fma(-r, y0, 1.0);
+  const double h = y0 * e;
+  const double p = __builtin_fma(e, 0.375, 0.5);
+  return __builtin_fma(h, p, y0);
 }
 
 // Per-row running state of FAST Compute.

@@ -2,28 +2,39 @@
 // (update or downdate of one factor by a caller-owned V), continuous batching
 // onto one GPU.
 //
-// A worker thread forms batches of at most one request per factor (the
-// oldest not yet launched; requests of one factor run in arrival order, in
-// successive batches, which the single stream keeps ordered) and enqueues
-// each batch with the batched schedule.  Two batch slots, each with its own
-// workspace, info words and staging buffer, let the next batch be enqueued
-// while the previous one runs.  Admission: a request whose batch workspace
-// would exceed the slot's workspace waits for the next batch; a request that
-// cannot fit even alone fails with CHOLMOD_ERR_ARG.  A request completes when
-// the step that ends its factor's work in the batch has run: after that
-// step's launch the worker enqueues the copy of those factors' info words
-// and an event, so small factors batched with large ones complete early.  A
-// request's latency is the host time from its submission to the worker
-// seeing that event.
+// Admission by HBM footprint.  The server owns one device arena of
+// cfg->ws_bytes bytes (its HBM budget besides the factors).  A worker thread
+// forms a batch from the waiting requests, oldest first, at most one per
+// factor and none of a factor whose previous request is still running (a
+// factor's requests run in submission order), taking each request whose
+// workspace (its private copy of V and its rotation records) still fits
+// into the free part of the arena; a request that could not fit even into
+// an empty arena fails with CHOLMOD_ERR_ARG.  The batch takes its arena
+// range, one of the server's streams and runs as one persistent launch (the
+// queued batch of cholmod_update_batched, so each result is bit for bit the
+// single-factor result).
+//
+// Overlap.  Up to cfg->streams batches are in flight at once, each on its own
+// stream: a batch formed while others run is launched at once, and its
+// workgroups take the compute units that the running batches' workgroups
+// leave (a launch holds at most one workgroup per unit of work, so a small
+// batch runs beside a large one, and a new batch fills the tail of an old
+// one).
+//
+// Completion.  The last workgroup to finish a factor of the batch writes
+// the factor's info word into host-mapped memory; the worker sees it and
+// completes that request while the rest of the batch still runs, and the
+// factor can take its next request at once.  A request's latency is the
+// host time from its submission to that point.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
-#include <functional>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -35,6 +46,11 @@
 namespace {
 
 using Clock = std::chrono::steady_clock;
+constexpr size_t kAlign = 256;
+constexpr int kMaxStreams = 16;
+constexpr int64_t kDoneEmpty = INT64_MIN;  // a done word not yet written
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Request {
   int32_t factor;
@@ -51,31 +67,68 @@ struct Factor {
   void* L;
   int64_t n, ldl;
   int32_t dtype;
-  std::deque<uint64_t> queue;  // tickets not yet launched, in arrival order
+  bool busy = false;  // a request of this factor is in flight
 };
 
-// Requests of a batch that complete together: those whose factors end at
-// the same step.
-constexpr int kMaxGroups = 32;
+// First-fit allocator over the arena's byte range.
+class Arena {
+ public:
+  void reset(size_t bytes) {
+    free_.clear();
+    if (bytes) free_[0] = bytes;
+  }
+  size_t largest() const {
+    size_t m = 0;
+    for (const auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t at = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
 
-struct Group {
-  hipEvent_t ev = nullptr;
-  std::vector<size_t> idx;  // positions in the slot's batch
+ private:
+  std::map<size_t, size_t> free_;  // offset -> bytes
 };
 
+// One stream with the batch that runs on it.
 struct Slot {
-  void* ws = nullptr;
-  int64_t* d_info = nullptr;
-  int64_t* h_info = nullptr;  // pinned
-  void* stage = nullptr;      // pinned
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;  // the batch's launches and info copy have run
+  int64_t* h_info = nullptr;  // pinned: info words copied back after the batch
+  int64_t* h_done = nullptr;  // pinned, mapped: per-factor done words
+  int64_t* d_done = nullptr;  // device address of h_done
+  void* stage = nullptr;      // pinned: the batch tables
   size_t stage_bytes = 0;
-  hipEvent_t done = nullptr;
   bool busy = false;
+  size_t off = 0, bytes = 0;  // arena range
   std::vector<uint64_t> tickets;
   std::vector<int64_t> ks;
-  std::vector<char> retired;  // per position in the batch
-  Group groups[kMaxGroups];
-  int ngroups = 0, next_group = 0;
+  std::vector<char> retired;
+  size_t left = 0;  // requests not yet retired
 };
 
 }  // namespace
@@ -83,99 +136,115 @@ struct Slot {
 struct cholmod_server {
   cholmod_server_cfg cfg{};
   int device = 0;
-  hipStream_t stream = nullptr;
-  Slot slots[2];
+  size_t cap = 256;  // requests per batch
+  int nslots = 4;
+  char* arena_base = nullptr;
+  Arena arena;
+  Slot slots[kMaxStreams];
   std::mutex mu;
   std::condition_variable cv;
   std::vector<Factor> factors;
   std::unordered_map<uint64_t, Request> reqs;
+  std::deque<uint64_t> queue;  // waiting tickets, oldest first
   uint64_t next_ticket = 1;
-  size_t rr = 0;  // round-robin start over factors
-  int64_t in_queue = 0, in_flight = 0;
+  int64_t in_flight = 0;
   std::atomic<bool> stop{false};
   std::atomic<int> fatal{0};
   std::thread worker;
 
-  int init_slots() {
-    const size_t cap = cfg.max_batch > 0 ? (size_t)cfg.max_batch : 256;
-    for (Slot& s : slots) {
-      if (hipMalloc(&s.ws, cfg.ws_bytes) != hipSuccess) return CHOLMOD_ERR_HIP;
-      if (hipMalloc((void**)&s.d_info, cap * sizeof(int64_t)) != hipSuccess) return CHOLMOD_ERR_HIP;
-      if (hipHostMalloc((void**)&s.h_info, cap * sizeof(int64_t), hipHostMallocDefault) !=
-          hipSuccess)
+  int init() {
+    if (hipMalloc((void**)&arena_base, cfg.ws_bytes) != hipSuccess) return CHOLMOD_ERR_HIP;
+    arena.reset(cfg.ws_bytes);
+    for (int i = 0; i < nslots; ++i) {
+      Slot& s = slots[i];
+      if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess)
         return CHOLMOD_ERR_HIP;
       if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
         return CHOLMOD_ERR_HIP;
-      for (Group& g : s.groups)
-        if (hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess)
-          return CHOLMOD_ERR_HIP;
+      if (hipHostMalloc((void**)&s.h_info, cap * sizeof(int64_t), hipHostMallocDefault) !=
+          hipSuccess)
+        return CHOLMOD_ERR_HIP;
+      if (hipHostMalloc((void**)&s.h_done, cap * sizeof(int64_t),
+                        hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+        return CHOLMOD_ERR_HIP;
+      if (hipHostGetDevicePointer((void**)&s.d_done, s.h_done, 0) != hipSuccess)
+        return CHOLMOD_ERR_HIP;
     }
     return CHOLMOD_OK;
   }
 
   void release() {
     for (Slot& s : slots) {
-      if (s.ws) hipFree(s.ws);
-      if (s.d_info) hipFree(s.d_info);
       if (s.h_info) hipHostFree(s.h_info);
+      if (s.h_done) hipHostFree(s.h_done);
       if (s.stage) hipHostFree(s.stage);
       if (s.done) hipEventDestroy(s.done);
-      for (Group& g : s.groups)
-        if (g.ev) hipEventDestroy(g.ev);
+      if (s.stream) hipStreamDestroy(s.stream);
       s = Slot{};
     }
-    if (stream) hipStreamDestroy(stream);
-    stream = nullptr;
+    if (arena_base) hipFree(arena_base);
+    arena_base = nullptr;
   }
 
-  // Request at position i of slot s gets its status and latency.
-  void retire_one(Slot& s, size_t i, Clock::time_point now) {
-    if (s.retired[i]) return;
-    s.retired[i] = 1;
-    --in_flight;
-    auto it = reqs.find(s.tickets[i]);
-    if (it == reqs.end()) return;
-    Request& r = it->second;
-    r.status = cholmod_decode_info(s.h_info[i], s.ks[i], nullptr, nullptr);
+  void finish(Request& r, int status, Clock::time_point now) {
+    r.status = status;
     r.latency = std::chrono::duration<double>(now - r.t_submit).count();
     r.done = true;
   }
 
-  // Groups whose events have fired, in step order; then the whole slot.
+  // Request at position i of slot s completes with the raw info word `info`.
+  void retire_one(Slot& s, size_t i, int64_t info, Clock::time_point now) {
+    if (s.retired[i]) return;
+    s.retired[i] = 1;
+    --s.left;
+    --in_flight;
+    auto it = reqs.find(s.tickets[i]);
+    if (it == reqs.end()) return;
+    Request& r = it->second;
+    factors[r.factor].busy = false;
+    finish(r, cholmod_decode_info(info, s.ks[i], nullptr, nullptr), now);
+  }
+
+  // Factors whose done word has been written; then the whole batch.
   bool poll_slot(Slot& s) {
     bool progress = false;
-    while (s.next_group < s.ngroups && hipEventQuery(s.groups[s.next_group].ev) == hipSuccess) {
-      const Clock::time_point now = Clock::now();
-      for (size_t i : s.groups[s.next_group].idx) retire_one(s, i, now);
-      ++s.next_group;
-      progress = true;
+    const Clock::time_point now = Clock::now();
+    for (size_t i = 0; i < s.tickets.size(); ++i) {
+      if (s.retired[i]) continue;
+      const int64_t w = __atomic_load_n(&s.h_done[i], __ATOMIC_ACQUIRE);
+      if (w != kDoneEmpty) {
+        retire_one(s, i, w, now);
+        progress = true;
+      }
     }
     if (hipEventQuery(s.done) == hipSuccess) {
-      const Clock::time_point now = Clock::now();
-      for (size_t i = 0; i < s.tickets.size(); ++i) retire_one(s, i, now);
+      for (size_t i = 0; i < s.tickets.size(); ++i) retire_one(s, i, s.h_info[i], now);
+      arena.release(s.off, s.bytes);
       s.tickets.clear();
       s.ks.clear();
       s.retired.clear();
-      s.ngroups = s.next_group = 0;
       s.busy = false;
       progress = true;
     }
     return progress;
   }
 
-  // Build and enqueue one batch into slot `s` (lock held).  Returns false
-  // if there was nothing to launch.
+  // Form a batch from the waiting requests and launch it on slot `s` (lock
+  // held).  Returns false if nothing was launched.
   bool launch(Slot& s) {
-    const size_t cap = cfg.max_batch > 0 ? (size_t)cfg.max_batch : 256;
     std::vector<cholmod_desc> descs;
     std::vector<uint64_t> tickets;
-    const size_t nf = factors.size();
-    for (size_t c = 0; c < nf && descs.size() < cap; ++c) {
-      const size_t f = (rr + c) % nf;
-      Factor& F = factors[f];
-      if (F.queue.empty()) continue;
-      const uint64_t t = F.queue.front();
-      Request& r = reqs[t];
+    std::vector<int32_t> taken;
+    const size_t room = arena.largest();
+    size_t need = 0;
+    const Clock::time_point now = Clock::now();
+    for (auto it = queue.begin(); it != queue.end() && descs.size() < cap;) {
+      Request& r = reqs[*it];
+      Factor& F = factors[r.factor];
+      if (F.busy || std::find(taken.begin(), taken.end(), r.factor) != taken.end()) {
+        ++it;
+        continue;
+      }
       cholmod_desc d;
       d.L = F.L;
       d.V = r.V;
@@ -185,93 +254,70 @@ struct cholmod_server {
       d.sigma = r.sigma;
       d.dtype = F.dtype;
       descs.push_back(d);
-      const size_t need = chm::batch_workspace_bytes(descs.data(), (int64_t)descs.size());
-      if (need == 0 || need > cfg.ws_bytes) {
+      const size_t plan = chm::batch_workspace_bytes(descs.data(), (int64_t)descs.size());
+      const size_t total = plan ? align_up(plan) + align_up(descs.size() * sizeof(int64_t)) : 0;
+      if (total == 0 || total > room) {
         descs.pop_back();
-        if (need == 0 || descs.empty()) {
-          // rejected by the planner, or cannot run even alone: it fails
-          // here rather than staying at the head of its factor's queue
-          F.queue.pop_front();
-          --in_queue;
-          r.status = CHOLMOD_ERR_ARG;
-          r.latency = std::chrono::duration<double>(Clock::now() - r.t_submit).count();
-          r.done = true;
+        cholmod_desc alone = d;
+        const size_t one = chm::batch_workspace_bytes(&alone, 1);
+        if (one == 0 || align_up(one) + kAlign > cfg.ws_bytes) {
+          // it can never run: it fails rather than blocking its factor
+          it = queue.erase(it);
+          finish(r, CHOLMOD_ERR_ARG, now);
+          continue;
         }
+        ++it;  // waits for memory to free up; smaller requests may go first
         continue;
       }
-      F.queue.pop_front();
-      --in_queue;
-      tickets.push_back(t);
+      need = total;
+      taken.push_back(r.factor);
+      tickets.push_back(*it);
+      it = queue.erase(it);
     }
-    rr = nf ? (rr + 1) % nf : 0;
     if (descs.empty()) return false;
     const int64_t count = (int64_t)descs.size();
+    size_t off = 0;
+    if (!arena.alloc(need, &off)) {  // cannot happen: need <= largest free range
+      for (uint64_t t : tickets) queue.push_front(t);
+      return false;
+    }
+    char* ws = arena_base + off;
+    const size_t plan = chm::batch_workspace_bytes(descs.data(), count);
+    int64_t* d_info = (int64_t*)(ws + align_up(plan));
     const size_t tb = chm::batch_table_bytes(descs.data(), count);
+    int rc = CHOLMOD_OK;
     if (s.stage_bytes < tb) {
       if (s.stage) hipHostFree(s.stage);
       s.stage = nullptr;
       s.stage_bytes = 0;
-      if (hipHostMalloc(&s.stage, tb, hipHostMallocDefault) != hipSuccess) {
-        fatal = CHOLMOD_ERR_HIP;
-        return false;
-      }
-      s.stage_bytes = tb;
+      if (hipHostMalloc(&s.stage, tb, hipHostMallocDefault) != hipSuccess) rc = CHOLMOD_ERR_HIP;
+      else s.stage_bytes = tb;
     }
-    // completion groups: the requests whose factors end at the same step
-    // (factors without steps are final after the preparation launch, so with
-    // those of step 0); beyond kMaxGroups - 1 distinct steps the rest
-    // complete with the slot
-    std::vector<int64_t> last(count);
-    std::vector<int64_t> ends;
-    for (int64_t i = 0; i < count; ++i) {
-      const int64_t st_i = chm::batch_steps_of(descs[i]);
-      last[i] = st_i > 0 ? st_i - 1 : 0;
-      ends.push_back(last[i]);
-    }
-    std::sort(ends.begin(), ends.end());
-    ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
-    if ((int)ends.size() > kMaxGroups - 1) ends.resize(kMaxGroups - 1);
-    s.ngroups = (int)ends.size();
-    s.next_group = 0;
-    for (int g = 0; g < s.ngroups; ++g) s.groups[g].idx.clear();
-    for (int64_t i = 0; i < count; ++i) {
-      const auto it = std::lower_bound(ends.begin(), ends.end(), last[i]);
-      if (it != ends.end() && *it == last[i]) s.groups[it - ends.begin()].idx.push_back((size_t)i);
-    }
-    int g_next = 0;
-    const std::function<int(int64_t)> after_step = [&](int64_t step) -> int {
-      while (g_next < s.ngroups && ends[g_next] == step) {
-        for (size_t i : s.groups[g_next].idx)
-          if (hipMemcpyAsync(s.h_info + i, s.d_info + i, sizeof(int64_t), hipMemcpyDeviceToHost,
-                             stream) != hipSuccess)
-            return CHOLMOD_ERR_HIP;
-        if (hipEventRecord(s.groups[g_next].ev, stream) != hipSuccess) return CHOLMOD_ERR_HIP;
-        ++g_next;
-      }
-      return CHOLMOD_OK;
-    };
-    int rc = chm::enqueue_batch(descs.data(), count, s.ws, cfg.ws_bytes, s.d_info, stream,
-                                s.stage, s.stage_bytes, &after_step);
-    // groups never reached (a stopped enqueue) complete with the slot
-    s.ngroups = g_next;
+    for (int64_t i = 0; i < count; ++i) s.h_done[i] = kDoneEmpty;
+    if (rc == CHOLMOD_OK)
+      rc = chm::enqueue_batch(descs.data(), count, ws, plan, d_info, s.stream, s.stage,
+                              s.stage_bytes, nullptr, s.d_done);
     if (rc == CHOLMOD_OK &&
-        hipMemcpyAsync(s.h_info, s.d_info, count * sizeof(int64_t), hipMemcpyDeviceToHost,
-                       stream) != hipSuccess)
+        hipMemcpyAsync(s.h_info, d_info, count * sizeof(int64_t), hipMemcpyDeviceToHost,
+                       s.stream) != hipSuccess)
       rc = CHOLMOD_ERR_HIP;
-    if (rc == CHOLMOD_OK && hipEventRecord(s.done, stream) != hipSuccess) rc = CHOLMOD_ERR_HIP;
+    if (rc == CHOLMOD_OK && hipEventRecord(s.done, s.stream) != hipSuccess) rc = CHOLMOD_ERR_HIP;
     if (rc != CHOLMOD_OK) {
-      for (uint64_t t : tickets) {
-        Request& r = reqs[t];
-        r.status = rc;
-        r.done = true;
-      }
+      // nothing may still run on this range if enqueueing failed part way
+      hipStreamSynchronize(s.stream);
+      arena.release(off, need);
+      for (uint64_t t : tickets) finish(reqs[t], rc, now);
       if (rc == CHOLMOD_ERR_HIP) fatal = rc;
       return true;
     }
+    s.off = off;
+    s.bytes = need;
     s.tickets = std::move(tickets);
     s.ks.clear();
     for (const cholmod_desc& d : descs) s.ks.push_back(d.k);
     s.retired.assign(s.tickets.size(), 0);
+    s.left = s.tickets.size();
+    for (int32_t f : taken) factors[f].busy = true;
     s.busy = true;
     in_flight += count;
     return true;
@@ -282,23 +328,23 @@ struct cholmod_server {
     std::unique_lock<std::mutex> lk(mu);
     while (!stop) {
       bool progress = false;
-      for (Slot& s : slots) {
-        if (s.busy) progress |= poll_slot(s);
-      }
-      if (in_queue > 0 && !fatal) {
-        for (Slot& s : slots) {
-          if (!s.busy && in_queue > 0) progress |= launch(s);
-        }
+      for (int i = 0; i < nslots; ++i)
+        if (slots[i].busy) progress |= poll_slot(slots[i]);
+      if (!queue.empty() && !fatal) {
+        for (int i = 0; i < nslots && !queue.empty(); ++i)
+          if (!slots[i].busy) progress |= launch(slots[i]);
       }
       cv.notify_all();  // drain() and destroy() wait on the counters
       if (!progress) {
         if (in_flight > 0) {
-          // a batch is running: look again shortly
+          // batches are running: look again shortly
           lk.unlock();
           std::this_thread::sleep_for(std::chrono::microseconds(20));
           lk.lock();
         } else {
-          cv.wait(lk, [&] { return stop.load() || in_queue > 0; });
+          // wake on a submission; requests waiting for memory or for their
+          // factor always have a batch in flight ahead of them
+          cv.wait(lk, [&] { return stop.load() || (!queue.empty() && in_flight == 0); });
         }
       }
     }
@@ -311,20 +357,19 @@ int cholmod_server_create(const cholmod_server_cfg* cfg, cholmod_server** out) {
   if (cfg == nullptr || out == nullptr) return CHOLMOD_ERR_ARG;
   if (cfg->ws_bytes < 4096 || cfg->max_batch < 0 || cfg->max_batch > 65535)
     return CHOLMOD_ERR_ARG;
+  if (cfg->streams < 0 || cfg->streams > kMaxStreams) return CHOLMOD_ERR_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess) return CHOLMOD_ERR_HIP;
   if (cfg->device < 0 || cfg->device >= ndev) return CHOLMOD_ERR_ARG;
   cholmod_server* s = new cholmod_server();
   s->cfg = *cfg;
-  s->cfg.ws_bytes = cfg->ws_bytes / 256 * 256;
+  s->cfg.ws_bytes = cfg->ws_bytes / kAlign * kAlign;
   s->device = cfg->device;
+  s->cap = cfg->max_batch > 0 ? (size_t)cfg->max_batch : 256;
+  s->nslots = cfg->streams > 0 ? cfg->streams : 4;
   int prev = 0;
   hipGetDevice(&prev);
-  int rc = CHOLMOD_OK;
-  if (hipSetDevice(s->device) != hipSuccess ||
-      hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
-    rc = CHOLMOD_ERR_HIP;
-  if (rc == CHOLMOD_OK) rc = s->init_slots();
+  int rc = hipSetDevice(s->device) == hipSuccess ? s->init() : CHOLMOD_ERR_HIP;
   hipSetDevice(prev);
   if (rc != CHOLMOD_OK) {
     s->release();
@@ -390,8 +435,7 @@ int cholmod_server_submit(cholmod_server* s, int32_t id, const void* V, int64_t 
   r.sigma = sigma;
   r.t_submit = Clock::now();
   s->reqs.emplace(t, r);
-  F.queue.push_back(t);
-  ++s->in_queue;
+  s->queue.push_back(t);
   *ticket = t;
   s->cv.notify_all();
   return CHOLMOD_OK;
@@ -412,7 +456,7 @@ int cholmod_server_poll(cholmod_server* s, uint64_t ticket, int* status, double*
 int cholmod_server_drain(cholmod_server* s) {
   if (s == nullptr) return CHOLMOD_ERR_ARG;
   std::unique_lock<std::mutex> lk(s->mu);
-  s->cv.wait(lk, [&] { return s->fatal != 0 || (s->in_queue == 0 && s->in_flight == 0); });
+  s->cv.wait(lk, [&] { return s->fatal != 0 || (s->queue.empty() && s->in_flight == 0); });
   return s->fatal;
 }
 
@@ -420,7 +464,7 @@ int cholmod_server_destroy(cholmod_server* s) {
   if (s == nullptr) return CHOLMOD_ERR_ARG;
   {
     std::unique_lock<std::mutex> lk(s->mu);
-    s->cv.wait(lk, [&] { return s->fatal != 0 || (s->in_queue == 0 && s->in_flight == 0); });
+    s->cv.wait(lk, [&] { return s->fatal != 0 || (s->queue.empty() && s->in_flight == 0); });
     s->stop = true;
     s->cv.notify_all();
   }
@@ -428,7 +472,8 @@ int cholmod_server_destroy(cholmod_server* s) {
   int prev = 0;
   hipGetDevice(&prev);
   hipSetDevice(s->device);
-  hipStreamSynchronize(s->stream);
+  for (int i = 0; i < s->nslots; ++i)
+    if (s->slots[i].stream) hipStreamSynchronize(s->slots[i].stream);
   s->release();
   hipSetDevice(prev);
   delete s;

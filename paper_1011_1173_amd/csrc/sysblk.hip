@@ -86,9 +86,15 @@ struct alignas(4 * sizeof(ST)) GRec {
   ST c, s, ic, ss;
 };
 
-// Original diagonal of a row, with the values its first Compute starts from.
-struct DiagPre {
-  double l, t, il, pad;  // L_ii, L_ii * L_ii, 1 / L_ii
+// What lane 0 of the chain starts row r from: the row's original diagonal
+// (the values its first Compute uses) and the originals L(r-1, r+1), L(r, r+1)
+// of the two rows it applies to column r+1.  48 bytes, so that one step reads
+// it with three LDS loads.
+struct Feed {
+  double t, il;  // L_rr * L_rr, 1 / L_rr
+  double l, lo;  // L_rr, L(r-1, r+1)
+  double hi;     // L(r, r+1)
+  double pad;
 };
 
 // What wave 0 produces at its step of row i: L(i-1, i+1), L(i, i+1), L(i, i).
@@ -96,11 +102,6 @@ struct Band {
   double lo, hi, d, pad;
 };
 
-// Lane 0's other inputs at step t: the originals L(t-1, t+1) and L(t, t+1)
-// for the rows wave 0 applies to column t+1.
-struct Fill {
-  double lo, hi;
-};
 
 struct SbLds {
   // first, so that every record is within the 64 KB reach of an LDS
@@ -119,8 +120,7 @@ struct SbLds {
   double Hb[kKP][2][kBR];   // V_j[m] after each helper rotation, by step parity
   double X[5][2][kBR];      // helper h -> h+1, by step parity
   Band Lc[kRRows];          // wave 0 results by row + 16
-  DiagPre dg[kRRows];       // by row; rows >= bbc unused
-  Fill fl[kRRows];           // by step; steps with t + 1 >= bbc unused
+  Feed fd[kRRows];          // by row; rows >= bbc unused
   int64_t lim;              // first failing row known at launch
   int fail;                 // first failing (row * 16 + column) of the block
   int tk;                   // owner schedule: this workgroup's ticket
@@ -378,34 +378,47 @@ struct ChainState {
   double v;            // V_i[m] for this step's Compute
   double lo, hi;       // L(i-1, i+1) and L(i, i+1) rotated through columns < m
   double pc, ps, pic;  // this lane's record {c, s, 1/c} of row i-1
+  double bx0, bx1, bw; // band of the previous step, stored at the next one
 };
 
 __device__ __forceinline__ void chain_init(SbLds& sh, ChainState& g, int lane) {
-  const DiagPre d0 = sh.dg[0];
-  g.tp = d0.t;
-  g.il = d0.il;
-  g.lin = d0.l;
+  const Feed f0 = sh.fd[0];
+  g.tp = f0.t;
+  g.il = f0.il;
+  g.lin = f0.l;
   g.v = sh.Hb[lane & 15][1][0];
-  g.lo = sh.fl[0].lo;
-  g.hi = sh.fl[0].hi;
+  g.lo = f0.lo;
+  g.hi = f0.hi;
   g.pc = 1.0;
   g.ps = 0.0;
   g.pic = 1.0;
+  g.bx0 = g.bx1 = g.bw = 0.0;
 }
 
-// One step of wave 0.  All 64 lanes compute; lanes m >= kc carry garbage
-// and send their LDS writes to rows nobody reads (record row kRRows - 1,
-// band row 0).  CHECK: the pipeline is filling or draining (some lane has
-// i < 0, or i + 1 >= bbc).
-template <bool CHECK, int SG>
-__device__ __forceinline__ void chain_step(SbLds& sh, ChainState& g, int t, int m, int kc,
-                                           int bbc) {
-  const int i = t - m;
-  const int jj = i + 1;
-  const bool act = m < kc;
-  double Wc = sh.Hb[m & 15][(t - 1) & 1][jj & 63];
-  const DiagPre dn = sh.dg[t + 1];  // t + 1 < 80
-  const Fill fn = sh.fl[t + 1];
+// One step t of wave 0, lane m < kc (the wave runs with the other lanes
+// masked off): Compute(i, m) for i = t - m, then the Apply of rows i-1 (the
+// lane's record of the previous step) and i to column i+1, whose V_{i+1}[m]
+// after rows < i-1 the helpers left in Hb at the previous step.  Reads state
+// g, writes state o (the caller alternates two states, so nothing is copied
+// between steps).  hb: this lane's Hb value for the step; rec, band: where
+// the lane's record and band go (row i + 16); fn: row t+1's feed, the values
+// lane 0 takes at the next step.
+//
+// FILL (the first kc - 1 steps): lanes with i < 0 have not started; they
+// keep their state, write identity records into the pad rows before the
+// block and pass identity values on.  In every other step each lane
+// computes: lanes whose row i is at or after the block's last row compute
+// rows nobody reads (their records and bands land in the pad rows after the
+// block, their Hb reads stay inside LDS), and values of such rows only flow
+// to rows after them.
+template <bool FILL, int SG, typename RP, typename BP>
+__device__ __forceinline__ void chain_step(const ChainState& g, ChainState& o, double Wc,
+                                           const Feed fn, RP rec, BP band, bool started) {
+  // the previous step's band: nobody reads it during the chain, so it is
+  // stored here, where its LDS latency overlaps this step's Compute
+  band[-1].lo = g.bx0;
+  band[-1].hi = g.bx1;
+  band[-1].d = g.bw;
   // Compute(i, m)
   const double v = g.v;
   const double tt = __builtin_fma(SG * v, v, g.tp);
@@ -414,36 +427,43 @@ __device__ __forceinline__ void chain_step(SbLds& sh, ChainState& g, int t, int 
   const double s = v * g.il;
   const double c = ww * g.il;
   const double ic = g.lin * y;
-  RotRec cur;
-  cur.c = c; cur.s = s; cur.ic = ic; cur.ss = SG * s;
-  const bool rec_ok = act && (!CHECK || (i >= 0 && i < bbc));
-  sh.R[rec_ok ? i + kPad : kRRows - 1][m & 15] = cur;
-  // rows i-1 (record of the previous step) and i applied to column jj
+  // the record goes out as soon as it exists: the helpers read it after this
+  // step's barrier, which waits for the store
+  if (FILL) {
+    rec->c = started ? c : 1.0;
+    rec->s = started ? s : 0.0;
+    rec->ic = started ? ic : 1.0;
+  } else {
+    rec->c = c;
+    rec->s = s;
+    rec->ic = ic;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  o.tp = sb_shr1(tt, fn.t);
+  o.il = sb_shr1(y, fn.il);
+  o.lin = sb_shr1(ww, fn.l);  // L_ii after column m = t * y: what tp * il gives lane m+1
+  // rows i-1 (record of the previous step) and i applied to column i+1
   const double x0 = __builtin_fma(SG * g.ps, Wc, g.lo) * g.pic;
   Wc = __builtin_fma(-g.ps, x0, g.pc * Wc);
   const double x1 = __builtin_fma(SG * s, Wc, g.hi) * ic;
   Wc = __builtin_fma(-s, x1, c * Wc);
-  Band b;
-  b.lo = x0; b.hi = x1; b.d = ww; b.pad = 0.0;
-  sh.Lc[act ? (CHECK ? imax(imin(i + kPad, kRRows - 1), 0) : i + kPad) : 0] = b;
-  if (CHECK) {
-    const bool started = i >= 0;
-    g.v = started ? Wc : v;
-    g.pc = started ? c : 1.0;
-    g.ps = started ? s : 0.0;
-    g.pic = started ? ic : 1.0;
+  if (FILL) {
+    o.v = started ? Wc : v;
+    o.pc = started ? c : 1.0;
+    o.ps = started ? s : 0.0;
+    o.pic = started ? ic : 1.0;
   } else {
-    g.v = Wc;
-    g.pc = c;
-    g.ps = s;
-    g.pic = ic;
+    o.v = Wc;
+    o.pc = c;
+    o.ps = s;
+    o.pic = ic;
   }
+  o.bx0 = x0;
+  o.bx1 = x1;
+  o.bw = ww;
   // to lane m+1 (lane 0 takes row t+1's originals)
-  g.lo = sb_shr1(x0, fn.lo);
-  g.hi = sb_shr1(x1, fn.hi);
-  g.tp = sb_shr1(tt, dn.t);
-  g.il = sb_shr1(y, dn.il);
-  g.lin = sb_shr1(ww, dn.l);  // L_ii after column m = t * y: what tp * il gives lane m+1
+  o.lo = sb_shr1(x0, fn.lo);
+  o.hi = sb_shr1(x1, fn.hi);
 }
 
 // Helper wave layout (columns [MLO, MLO + CNT) of V, lane jj = block column):
@@ -493,15 +513,93 @@ __device__ __forceinline__ void helper_step(SbLds& sh, double (&st)[kSt], int t,
   if (H == 0) st[2 * CNT] = sh.Lb[imin(t, kBR - 1)][jj];
 }
 
-// Each role runs its own step loop; every loop passes the same number of
-// barriers, one per step (the role is wave-uniform, so no wave enters
-// another role's loop).
-template <bool CHECK, int SG>
-__device__ __forceinline__ void chain_steps(SbLds& sh, ChainState& g, int t0, int t1,
-                                            int lane, int kc, int bbc) {
-  for (int t = t0; t < t1; ++t) {
-    chain_step<CHECK, SG>(sh, g, t, lane, kc, bbc);
+// LDS pointers that the compiler must keep in a register as they are (it
+// would otherwise re-add the array's base address, which is too large for an
+// LDS instruction's immediate offset, at every access).
+template <typename T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+
+template <typename T>
+__device__ __forceinline__ lds_ptr<T> lds_pin(const void* p) {
+  uint32_t a = (uint32_t)(uintptr_t)(lds_ptr<const char>)p;
+  asm volatile("" : "+v"(a));
+  return (lds_ptr<T>)(uintptr_t)a;
+}
+
+__device__ __forceinline__ Feed load_feed(lds_ptr<const Feed> p, int i) {
+  const lds_ptr<const double> d = (lds_ptr<const double>)(p + i);
+  Feed f;
+  f.t = d[0];
+  f.il = d[1];
+  f.l = d[2];
+  f.lo = d[3];
+  f.hi = d[4];
+  f.pad = 0.0;
+  return f;
+}
+
+// Wave 0's step loop over steps [0, nsteps), one barrier per step; lanes
+// m < kc compute, the others only pass the barriers.  Per lane the LDS
+// addresses of step t are fixed offsets plus t: Hb[m][(t-1) & 1][t - m + 1],
+// R[t - m + 16][m], Lc[t - m + 16], fd[t + 1].  Steps run in pairs with the
+// two states alternating; the pairs start on an even step, so step parity
+// (Hb's buffer) is known statically.  The feeds of a pair are read before
+// its first step, so their load latency is hidden.
+template <int SG>
+__device__ __forceinline__ void chain_wave0(SbLds& sh, int m, int kc, int nsteps) {
+  const bool act = m < kc;
+  const int ml = m & 15;
+  ChainState ga, gb;
+  chain_init(sh, ga, ml);
+  __syncthreads();
+  // + t + 64 * parity of t-1
+  lds_ptr<const double> hb = lds_pin<const double>(&sh.Hb[0][0][0] + 128 * ml + 1 - ml);
+  lds_ptr<RotRec> rec = lds_pin<RotRec>(&sh.R[0][0] + kPad * kKP - (kKP - 1) * ml);  // + 16 t
+  lds_ptr<Band> band = lds_pin<Band>(&sh.Lc[kPad] - ml);                            // + t
+  lds_ptr<const Feed> fd = lds_pin<const Feed>(&sh.fd[1]);                          // + t
+  int t = 0;
+  // fill: steps [0, kc - 1), in pairs, then the odd one
+  // No barrier may sit inside a branch on `act`: a wave with lanes on both
+  // sides would execute both sides' barriers.
+  for (; t + 2 <= kc - 1; t += 2) {
+    const Feed f0 = load_feed(fd, 0), f1 = load_feed(fd, 1);
+    if (act) chain_step<true, SG>(ga, gb, hb[64], f0, rec, band, t >= ml);
     __syncthreads();
+    if (act) chain_step<true, SG>(gb, ga, hb[1], f1, rec + kKP, band + 1, t + 1 >= ml);
+    __syncthreads();
+    hb += 2; rec += 2 * kKP; band += 2; fd += 2;
+  }
+  if (t < kc - 1) {  // t even
+    if (act) chain_step<true, SG>(ga, gb, hb[64], load_feed(fd, 0), rec, band, t >= ml);
+    __syncthreads();
+    ga = gb;
+    ++t; hb += 1; rec += kKP; band += 1; fd += 1;
+  }
+  if (t < nsteps && (t & 1)) {  // align the pairs to an even step
+    if (act) chain_step<false, SG>(ga, gb, hb[0], load_feed(fd, 0), rec, band, true);
+    __syncthreads();
+    ga = gb;
+    ++t; hb += 1; rec += kKP; band += 1; fd += 1;
+  }
+  for (; t + 2 <= nsteps; t += 2) {
+    const Feed f0 = load_feed(fd, 0), f1 = load_feed(fd, 1);
+    if (act) chain_step<false, SG>(ga, gb, hb[64], f0, rec, band, true);
+    __syncthreads();
+    if (act) chain_step<false, SG>(gb, ga, hb[1], f1, rec + kKP, band + 1, true);
+    __syncthreads();
+    hb += 2; rec += 2 * kKP; band += 2; fd += 2;
+  }
+  if (t < nsteps) {
+    if (act) chain_step<false, SG>(ga, gb, hb[64], load_feed(fd, 0), rec, band, true);
+    __syncthreads();
+    ga = gb;
+    band += 1;
+  }
+  // the last step's band (read after the caller's next barrier)
+  if (act) {
+    band[-1].lo = ga.bx0;
+    band[-1].hi = ga.bx1;
+    band[-1].d = ga.bw;
   }
 }
 
@@ -526,17 +624,15 @@ __device__ __forceinline__ void chain_setup_tri(SbLds& sh, int bbc) {
   if (tid < kRRows) {
     const int r = tid < kBR ? tid : kBR - 1;
     const double l = sh.Lb[r][r];
-    DiagPre d;
-    d.l = l;
-    d.t = l * l;
-    d.il = 1.0 / l;
-    d.pad = 0.0;
-    sh.dg[tid] = d;
+    Feed f;
+    f.l = l;
+    f.t = l * l;
+    f.il = 1.0 / l;
     // lane 0 at step t applies rows t-1 and t to column t+1
-    Fill f;
     f.lo = (tid >= 1 && tid + 1 < bbc) ? sh.Lb[tid - 1][tid + 1] : 0.0;
     f.hi = (tid + 1 < bbc) ? sh.Lb[tid][tid + 1] : 0.0;
-    sh.fl[tid] = f;
+    f.pad = 0.0;
+    sh.fd[tid] = f;
   }
 }
 
@@ -573,16 +669,9 @@ __device__ __forceinline__ void chain_loops(SbLds& sh, int kc, int bbc, bool pub
                                             GRec<ST>* __restrict__ T, int64_t pc) {
   const int tid = threadIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  // steady steps [s0, s1): every lane m < kc has i >= 0 and i + 1 < bbc
   const int nsteps = bbc + kc - 1;
-  const int s0 = kc - 1, s1 = imax(kc - 1, bbc - 1);
   if (wv == 0) {
-    ChainState g;
-    chain_init(sh, g, lane);
-    __syncthreads();
-    chain_steps<true, SG>(sh, g, 0, s0, lane, kc, bbc);
-    chain_steps<false, SG>(sh, g, s0, s1, lane, kc, bbc);
-    chain_steps<true, SG>(sh, g, s1, nsteps, lane, kc, bbc);
+    chain_wave0<SG>(sh, lane, kc, nsteps);
   } else if (wv == 4) {
     // shares its SIMD with wave 0: passes the same barriers and publishes
     int q = 0;
@@ -613,12 +702,15 @@ __device__ __forceinline__ void chain_loops(SbLds& sh, int kc, int bbc, bool pub
 // for column 0, the original diagonal is not > 0 (then c = w / L_ii is
 // negative, infinite or NaN); every later Compute of the same row or of a
 // later row may be garbage, none of an earlier row is.  So the failure is
-// the first record whose c is not a finite positive number.
+// the first record whose c is not a finite positive number.  store: the
+// triangle goes to L; otherwise (another pass of the same block follows) it
+// goes back to sh.Lb, rounded to the storage type as a store and reload
+// would, so that the next pass starts from what L would hold.
 template <typename ST>
 __device__ __forceinline__ void chain_finish(SbLds& sh, ST* __restrict__ L, int64_t ldl, int kc,
                                              int64_t kfull, int64_t m0, int64_t pc, int bbc,
                                              int64_t* __restrict__ info,
-                                             int64_t* __restrict__ stop_row) {
+                                             int64_t* __restrict__ stop_row, bool store = true) {
   const int tid = threadIdx.x;
   for (int idx = tid; idx < kBR * kKP; idx += kThreads) {
     const int r = idx >> 4, m = idx & 15;
@@ -630,7 +722,7 @@ __device__ __forceinline__ void chain_finish(SbLds& sh, ST* __restrict__ L, int6
   __syncthreads();
   if (tid == 0 && sh.fail != 0x7fffffff) {
     const int r = sh.fail >> 4, m = sh.fail & 15;
-    const int64_t code = (m == 0 && !(sh.dg[r].l > 0.0)) ? kCodeBadDiag : kCodeNotPD;
+    const int64_t code = (m == 0 && !(sh.fd[r].l > 0.0)) ? kCodeBadDiag : kCodeNotPD;
     atomicMin((unsigned long long*)info,
               (unsigned long long)info_key((pc + r) * kfull + m0 + m, code));
     atomicMin((unsigned long long*)stop_row, (unsigned long long)(pc + r));
@@ -645,7 +737,8 @@ __device__ __forceinline__ void chain_finish(SbLds& sh, ST* __restrict__ L, int6
       else if (j == i + 1) x = sh.Lc[i + kPad].hi;
       else if (j == i + 2) x = sh.Lc[i + 1 + kPad].lo;
       else x = sh.Lh[i + kPad][j];
-      L[(pc + i) * ldl + pc + j] = (ST)x;
+      if (store) L[(pc + i) * ldl + pc + j] = (ST)x;
+      else sh.Lb[i][j] = (double)(ST)x;
     }
   }
 }
@@ -955,31 +1048,34 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
   }
 }
 
+// One factor as the owner kernels see it.  Pass p (columns 16p .. of V)
+// keeps its records at T + p * n * 16.
+template <typename ST>
+struct OwnF {
+  ST* L;
+  const ST* W;  // private copy of V, row stride k
+  GRec<ST>* T;
+  int64_t* info;
+  int64_t* stop;
+  int64_t n, k, ldl;
+};
+
+// Pass `pass` of the owner of block j (the block's triangle is in sh.Lb):
+// apply blocks 0 .. j-1 of this pass to the block's columns as their owners
+// publish them, then the block's chain, publishing its records.  last: the
+// triangle goes to L, else back to sh.Lb for the next pass.
 template <int SG, typename ST, int KCF>
-__global__ __launch_bounds__(kThreads) void k_sb_owner(
-    ST* __restrict__ L, int64_t ldl, const ST* __restrict__ W, int64_t ldw, int kc_,
-    int64_t kfull, int64_t m0, int64_t n, GRec<ST>* __restrict__ T,
-    int64_t* __restrict__ info, int64_t* __restrict__ stop_row, int32_t* __restrict__ ticket) {
-  __shared__ SbLds sh;
-  const int kc = KCF ? KCF : kc_;
+__device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, int bbc,
+                                           int pass, bool last, int64_t deadline) {
   const int tid = threadIdx.x;
-  const int64_t deadline = wall_clock64() + kWaitTicks;
-  if (tid == 0) {
-    sh.tk = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    sh.tmo = 0;
-  }
-  __syncthreads();
-  const int j = sh.tk;
+  const int64_t m0 = (int64_t)pass * kKP;
+  const int kc = KCF ? KCF : (int)(F.k - m0 < kKP ? F.k - m0 : kKP);
   const int64_t pj = (int64_t)j * kBR;
-  const int bbc = n - pj < kBR ? (int)(n - pj) : kBR;
-  // every global input of the workgroup is issued before anything is staged:
-  // the block's triangle, V of its columns and the first tile
-  ST lt[kTilePerThread];
-#pragma unroll
-  for (int q = 0; q < kTilePerThread; ++q) {
-    const int idx = tid + q * kThreads, i = idx >> 6, c = idx & 63;
-    lt[q] = (i < bbc && c < bbc && c >= i) ? L[(pj + i) * ldl + pj + c] : (ST)0;
-  }
+  GRec<ST>* const T = F.T + (int64_t)pass * F.n * kKP;
+  const ST* const W = F.W + m0;
+  const int64_t ldw = F.k;
+  // every global input of the pass is issued before anything is staged: V
+  // of the block's columns and the first tile
   ST w[kOwnCols];
 #pragma unroll
   for (int k = 0; k < 2; ++k)
@@ -989,12 +1085,7 @@ __global__ __launch_bounds__(kThreads) void k_sb_owner(
       w[2 * k + u] = (tid < kOwnThreads && c < bbc && m < kc) ? W[(pj + c) * ldw + m] : (ST)0;
     }
   TileRegs<ST> tr;
-  if (j > 0) tile_issue_a(tr, L, ldl, 0, pj, bbc);
-#pragma unroll
-  for (int q = 0; q < kTilePerThread; ++q) {
-    const int idx = tid + q * kThreads;
-    sh.Lb[idx >> 6][idx & 63] = (double)lt[q];
-  }
+  if (j > 0) tile_issue_a(tr, F.L, F.ldl, 0, pj, bbc);
   // identity records everywhere: the pad rows keep them, each block's rows
   // are overwritten as they arrive
   for (int idx = tid; idx < kRRows * kKP; idx += kThreads) sh.R[idx >> 4][idx & 15] = identity_rec();
@@ -1003,7 +1094,7 @@ __global__ __launch_bounds__(kThreads) void k_sb_owner(
   for (int b = 0; b < j; ++b) {
     __syncthreads();  // sh.A is free again
     tile_stage(sh, tr);
-    if (b + 1 < j) tile_issue_a(tr, L, ldl, (int64_t)(b + 1) * kBR, pj, bbc);
+    if (b + 1 < j) tile_issue_a(tr, F.L, F.ldl, (int64_t)(b + 1) * kBR, pj, bbc);
     const int64_t pb = (int64_t)b * kBR;
     __syncthreads();
     owner_apply<SG, ST, KCF>(sh, kc, pb, w, T, deadline, b == j - 1);
@@ -1011,7 +1102,7 @@ __global__ __launch_bounds__(kThreads) void k_sb_owner(
 #pragma unroll
     for (int q = 0; q < kTilePerThread; ++q) {
       const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
-      if (c < bbc) L[(pb + r) * ldl + pj + c] = tile_a<ST>(sh)[r * kLdA + c];
+      if (c < bbc) F.L[(pb + r) * F.ldl + pj + c] = tile_a<ST>(sh)[r * kLdA + c];
     }
   }
   // V of the block's columns, after all earlier rows, starts the chain
@@ -1024,13 +1115,157 @@ __global__ __launch_bounds__(kThreads) void k_sb_owner(
         if (m < kc) sh.Hb[m][1][c] = c < bbc ? (double)w[2 * k + u] : 0.0;
       }
   }
-  if (bbc < kBR) chain_setup_records(sh);
   __syncthreads();
-  chain_loops<SG, ST, KCF>(sh, kc, bbc, pj + kBR < n, T, pj);
-  chain_finish(sh, L, ldl, kc, kfull, m0, pj, bbc, info, stop_row);
+  chain_loops<SG, ST, KCF>(sh, kc, bbc, pj + kBR < F.n, T, pj);
+  chain_finish(sh, F.L, F.ldl, kc, F.k, m0, pj, bbc, F.info, F.stop, last);
   if (tid == 0 && sh.tmo)
-    atomicMin((unsigned long long*)info,
-              (unsigned long long)info_key(pj * kfull + m0, kCodeTimeout));
+    atomicMin((unsigned long long*)F.info,
+              (unsigned long long)info_key(pj * F.k + m0, kCodeTimeout));
+  __syncthreads();
+}
+
+// Every pass of the owner of block j.  The passes of one block run in order;
+// the owners of different blocks run their passes concurrently, so pass p+1
+// of the factor trails pass p by about one block instead of starting after
+// it: the chains of all passes together take about (blocks + passes - 1)
+// block chains.
+template <int SG, typename ST, bool SPEC16>
+__device__ __forceinline__ void owner_item(SbLds& sh, const OwnF<ST>& F, int j) {
+  const int tid = threadIdx.x;
+  const int64_t deadline = wall_clock64() + kWaitTicks;
+  const int64_t pj = (int64_t)j * kBR;
+  const int bbc = F.n - pj < kBR ? (int)(F.n - pj) : kBR;
+  if (tid == 0) sh.tmo = 0;
+#pragma unroll
+  for (int q = 0; q < kTilePerThread; ++q) {
+    const int idx = tid + q * kThreads, i = idx >> 6, c = idx & 63;
+    sh.Lb[i][c] = (i < bbc && c < bbc && c >= i) ? (double)F.L[(pj + i) * F.ldl + pj + c] : 0.0;
+  }
+  const int passes = (int)((F.k + kKP - 1) / kKP);
+  for (int p = 0; p < passes; ++p) {
+    const bool last = p + 1 == passes;
+    if (SPEC16 && F.k - (int64_t)p * kKP >= kKP)
+      owner_pass<SG, ST, kKP>(sh, F, j, bbc, p, last, deadline);
+    else
+      owner_pass<SG, ST, 0>(sh, F, j, bbc, p, last, deadline);
+  }
+}
+
+// Workgroups take owner items from a counter until none are left: item j
+// owns the columns of block j.  An item waits only for items with lower
+// numbers, which were taken earlier and are running or done, so every wait
+// ends (each is still bounded, see kWaitTicks).
+template <int SG, typename ST>
+__global__ __launch_bounds__(kThreads) void k_sb_queue(OwnF<ST> F, int nitems,
+                                                       int32_t* __restrict__ ticket) {
+  __shared__ SbLds sh;
+  for (;;) {
+    if (threadIdx.x == 0)
+      sh.tk = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int j = sh.tk;
+    __syncthreads();
+    if (j >= nitems) break;
+    owner_item<SG, ST, true>(sh, F, j);
+  }
+}
+
+// The owner item (block j, every pass) of one factor of a queued batch.
+__device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int j) {
+  if (B.dtype == kStoreF64) {
+    OwnF<double> F;
+    F.L = (double*)B.L;
+    F.W = (const double*)B.W;
+    F.T = (GRec<double>*)B.T;
+    F.info = B.info;
+    F.stop = B.stop;
+    F.n = B.n;
+    F.k = B.k;
+    F.ldl = B.ldl;
+    if (B.sigma > 0) owner_item<1, double, true>(sh, F, j);
+    else owner_item<-1, double, true>(sh, F, j);
+  } else {
+    OwnF<float> F;
+    F.L = (float*)B.L;
+    F.W = (const float*)B.W;
+    F.T = (GRec<float>*)B.T;
+    F.info = B.info;
+    F.stop = B.stop;
+    F.n = B.n;
+    F.k = B.k;
+    F.ldl = B.ldl;
+    if (B.sigma > 0) owner_item<1, float, true>(sh, F, j);
+    else owner_item<-1, float, true>(sh, F, j);
+  }
+}
+
+// Batches: the same owner items over many factors, from one counter.  Item
+// t of the batch is (factor items[t].f, block items[t].j); the host orders
+// the items by block index, longest factor first within a block index, so
+// an item waits only for items of its factor with lower numbers.  When a
+// factor's last item finishes (its counter of unfinished items reaches
+// zero), the factor's L and info word are final; with a done word, that
+// workgroup copies the info word there (host-mapped memory) so that the
+// host can complete the factor while the batch still runs.
+__global__ __launch_bounds__(kThreads) void k_sb_qbatch(const BatchFactor* __restrict__ fac,
+                                                        const QItem* __restrict__ items,
+                                                        int nitems,
+                                                        int32_t* __restrict__ ticket) {
+  __shared__ SbLds sh;
+  for (;;) {
+    if (threadIdx.x == 0)
+      sh.tk = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int t = sh.tk;
+    __syncthreads();
+    if (t >= nitems) break;
+    const QItem it = items[t];
+    const BatchFactor B = fac[it.f];
+    qbatch_item(sh, B, it.j);  // ends with a barrier: every wave's stores are issued
+    if (threadIdx.x == 0 && B.done != nullptr) {
+      __threadfence();  // the workgroup's stores, device-wide
+      if (__hip_atomic_fetch_add(B.left, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+        const int64_t info =
+            __hip_atomic_load(B.info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(B.done, info, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+  }
+}
+
+// Preparation of a queued batch (grid (chunks, factors)): W <- V, info and
+// stop row reset, the records of every pass emptied; the batch's work
+// counter reset by the first workgroup.
+__global__ void k_prepare_qbatch(const BatchFactor* __restrict__ fac,
+                                 int32_t* __restrict__ ticket) {
+  const BatchFactor F = fac[blockIdx.y];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *F.info = INT64_MAX;
+    *F.stop = INT64_MAX;
+    if (blockIdx.y == 0) *ticket = 0;
+    const int32_t items = (F.n == 0 || F.k == 0) ? 0 : (int32_t)((F.n + kBR - 1) / kBR);
+    *F.left = items;
+    // a factor without items is final now
+    if (items == 0 && F.done != nullptr)
+      __hip_atomic_store(F.done, (int64_t)INT64_MAX, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  const bool f64 = F.dtype == kStoreF64;
+  const int64_t words = F.n * F.k * (f64 ? 2 : 1);  // 4-byte words
+  const uint32_t* __restrict__ src = (const uint32_t*)F.V;
+  uint32_t* __restrict__ dst = (uint32_t*)F.W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < words; i += stride) dst[i] = src[i];
+  // records: 16 per row and pass, 4 words of the storage type each
+  const int64_t passes = (F.k + kKP - 1) / kKP;
+  const int64_t rwords = F.n * kKP * 4 * passes;
+  if (f64) {
+    uint64_t* __restrict__ r = (uint64_t*)F.T;
+    for (int64_t i = i0; i < rwords; i += stride) r[i] = RecBits<double>::kEmpty;
+  } else {
+    uint32_t* __restrict__ r = (uint32_t*)F.T;
+    for (int64_t i = i0; i < rwords; i += stride) r[i] = RecBits<float>::kEmpty;
+  }
 }
 
 // Records of one pass start out empty.
@@ -1041,6 +1276,87 @@ __global__ void k_owner_clear(GRec<ST>* __restrict__ T, int64_t words) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
     p[i] = RecBits<ST>::kEmpty;
+}
+
+// ------------------------------------------------------- latency probes
+// The two latencies that bound one factor's time: the chain of a 64-row
+// block (wave 0's Compute + Apply per step plus the helpers, one barrier per
+// step) and the hand-off of a value from one workgroup to another through
+// device-scope memory (how an owner learns of the records it waits for).
+// Measurement only; nothing here is on the modification path.
+
+// One workgroup runs the chain of `blocks` synthetic 64-row blocks with kc
+// columns of V, back to back, everything in LDS (no global traffic), and
+// writes out[0] = steady-counter ticks (100 MHz) summed over the chains and
+// out[1] = shader-clock cycles summed over the chains.
+template <int KCF>
+__global__ __launch_bounds__(kThreads) void k_probe_chain(int kc, int blocks,
+                                                           int64_t* __restrict__ out) {
+  __shared__ SbLds sh;
+  const int tid = threadIdx.x;
+  // a well-conditioned upper triangle and small V values
+  for (int idx = tid; idx < kBR * kBR; idx += kThreads) {
+    const int i = idx >> 6, j = idx & 63;
+    sh.Lb[i][j] = j < i ? 0.0 : (j == i ? 8.0 + 0.01 * i : 1e-3 * (double)((i + 2 * j) % 11 - 5));
+  }
+  constexpr int kHbPerThread = kBR * kKP / kThreads;  // 2
+  double v0[kHbPerThread];
+#pragma unroll
+  for (int q = 0; q < kHbPerThread; ++q) {
+    const int idx = tid + q * kThreads, m = idx & 15, c = idx >> 4;
+    v0[q] = 1e-2 * (double)((3 * c + 5 * m) % 13 - 6);
+  }
+  int64_t ticks = 0, cyc = 0;
+  for (int b = 0; b < blocks; ++b) {
+#pragma unroll
+    for (int q = 0; q < kHbPerThread; ++q) {
+      const int idx = tid + q * kThreads;
+      sh.Hb[idx & 15][1][idx >> 4] = v0[q];
+    }
+    __syncthreads();
+    chain_setup(sh, kBR);
+    __syncthreads();
+    const int64_t w0 = wall_clock64(), c0 = clock64();
+    chain_loops<1, double, KCF>(sh, kc, kBR, false, (GRec<double>*)nullptr, 0);
+    __syncthreads();
+    ticks += wall_clock64() - w0;
+    cyc += clock64() - c0;
+  }
+  if (tid == 0) {
+    out[0] = ticks;
+    out[1] = cyc;
+  }
+}
+
+// Workgroups 0 and `peer` pass a counter back and forth `rounds` times
+// through device-scope stores and loads of two flag words (zero at launch);
+// other workgroups exit at once.  Workgroups are dispatched to the XCDs
+// round-robin, so peer = 1 crosses XCDs and peer = 8 stays on one.  Every
+// wait is bounded: out[0] = steady-counter ticks for all rounds, out[1] = 1
+// if a wait ran out.
+__global__ void k_probe_handoff(int rounds, int peer, int32_t* __restrict__ flags,
+                                int64_t* __restrict__ out) {
+  const int wg = blockIdx.x;
+  if ((wg != 0 && wg != peer) || threadIdx.x != 0) return;
+  int32_t* mine = flags + (wg == 0 ? 0 : 32);  // separate cache lines
+  int32_t* theirs = flags + (wg == 0 ? 32 : 0);
+  const int64_t t0 = wall_clock64();
+  const int64_t deadline = t0 + 100000000;  // 1 s
+  int bad = 0;
+  for (int r = 1; r <= rounds && !bad; ++r) {
+    if (wg == 0) __hip_atomic_store(mine, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (__hip_atomic_load(theirs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < r) {
+      if (wall_clock64() > deadline) {
+        bad = 1;
+        break;
+      }
+    }
+    if (wg != 0) __hip_atomic_store(mine, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (wg == 0) {
+    out[0] = wall_clock64() - t0;
+    out[1] = bad;
+  }
 }
 
 // Batched form: the launch of step s holds, for every factor with more than
@@ -1110,25 +1426,48 @@ __global__ void k_prepare_batch(const BatchFactor* __restrict__ fac) {
     dst[i] = src[i];
 }
 
-// One owner launch per pass; tickets[p] (zero before the first pass) counts
-// the workgroups of pass p as they start.
+// Compute units of the current device (cached per device): the owner
+// kernels hold one workgroup per CU, so a grid of that many covers the GPU.
+int owner_grid_limit() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    cached[dev] = cus;
+  }
+  return cached[dev];
+}
+
+// One persistent owner launch per modification; tickets[0] is zero before
+// it (the preparation launch clears it).  The records of every pass start
+// out empty.
 template <typename ST>
 hipError_t run_sysblk_t(hipStream_t st, ST* L, int64_t n, int64_t ldl, ST* W, int64_t k, int sg,
                         void* Tws, int64_t* info, int64_t* stop, int32_t* tickets) {
   GRec<ST>* R = reinterpret_cast<GRec<ST>*>(Tws);
   const int64_t nb = (n + kBR - 1) / kBR;
-  const int64_t words = n * kKP * 4;
+  const int64_t passes = (k + kKP - 1) / kKP;
+  const int64_t words = n * kKP * 4 * passes;
   const int64_t cblocks = (words + 255) / 256;
-  const unsigned cgrid = (unsigned)(cblocks < 1024 ? cblocks : 1024);
-  for (int64_t m0 = 0; m0 < k; m0 += kKP) {
-    const int kc = (int)((k - m0) < kKP ? (k - m0) : kKP);
-    hipLaunchKernelGGL(k_owner_clear<ST>, dim3(cgrid), dim3(256), 0, st, R, words);
-    // full passes (16 columns of V) use a variant specialised on that width
-    auto kern = sg > 0 ? (kc == kKP ? k_sb_owner<1, ST, kKP> : k_sb_owner<1, ST, 0>)
-                       : (kc == kKP ? k_sb_owner<-1, ST, kKP> : k_sb_owner<-1, ST, 0>);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreads), 0, st, L, ldl,
-                       (const ST*)(W + m0), k, kc, k, m0, n, R, info, stop, tickets + m0 / kKP);
-  }
+  const unsigned cgrid = (unsigned)(cblocks < 4096 ? cblocks : 4096);
+  hipLaunchKernelGGL(k_owner_clear<ST>, dim3(cgrid), dim3(256), 0, st, R, words);
+  OwnF<ST> F;
+  F.L = L;
+  F.W = W;
+  F.T = R;
+  F.info = info;
+  F.stop = stop;
+  F.n = n;
+  F.k = k;
+  F.ldl = ldl;
+  const int lim = owner_grid_limit();
+  const unsigned grid = (unsigned)(nb < lim ? nb : lim);
+  auto kern = sg > 0 ? k_sb_queue<1, ST> : k_sb_queue<-1, ST>;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, F, (int)nb, tickets);
   return hipGetLastError();
 }
 
@@ -1148,6 +1487,21 @@ hipError_t run_sysblk_batch_step(hipStream_t st, const BatchFactor* d_fac,
   if (S.nent > 0)
     hipLaunchKernelGGL(k_sb_batch, dim3((unsigned)(S.nent + S.nrest)), dim3(kThreads), 0, st,
                        d_fac, d_ent + S.off, (int)S.nent);
+  return hipGetLastError();
+}
+
+// A queued batch: the preparation launch and one persistent owner launch.
+hipError_t run_sysblk_qbatch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
+                             const QItem* d_items, int64_t nitems, int32_t* d_ticket) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prepare_qbatch, dim3(8, (unsigned)count), dim3(256), 0, st, d_fac,
+                     d_ticket);
+  if (nitems > 0) {
+    const int lim = owner_grid_limit();
+    const unsigned grid = (unsigned)(nitems < lim ? nitems : lim);
+    hipLaunchKernelGGL(k_sb_qbatch, dim3(grid), dim3(kThreads), 0, st, d_fac, d_items,
+                       (int)nitems, d_ticket);
+  }
   return hipGetLastError();
 }
 
@@ -1173,6 +1527,44 @@ hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double*
 hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, float* W, int64_t k,
                           double sg, void* T, int64_t* info, int64_t* stop, int32_t* tickets) {
   return run_sysblk_t<float>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets);
+}
+
+// Latency probes (see k_probe_chain, k_probe_handoff): out[0] ns per chain
+// step, out[1] ns per 64-row block's chain, out[2] / out[3] ns per one-way
+// hand-off across XCDs / within one XCD.  Synchronous on `st`.
+hipError_t run_probe_latency(hipStream_t st, int kc, int blocks, int rounds, double* out4,
+                             int* timed_out) {
+  void* buf = nullptr;
+  hipError_t e = hipMalloc(&buf, 4096);
+  if (e != hipSuccess) return e;
+  int64_t* d_out = (int64_t*)buf;
+  int32_t* flags = (int32_t*)((char*)buf + 1024);
+  int64_t h[6] = {0, 0, 0, 0, 0, 0};
+  *timed_out = 0;
+  do {
+    // the variant the owner schedule runs: specialised on 16 columns, or generic
+    auto kern = kc == kKP ? k_probe_chain<kKP> : k_probe_chain<0>;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(kThreads), 0, st, kc, blocks, d_out);
+    if ((e = hipGetLastError()) != hipSuccess) break;
+    for (int peer : {1, 8}) {
+      if ((e = hipMemsetAsync(flags, 0, 512, st)) != hipSuccess) break;
+      hipLaunchKernelGGL(k_probe_handoff, dim3(peer + 1), dim3(64), 0, st, rounds, peer, flags,
+                         d_out + (peer == 1 ? 2 : 4));
+      if ((e = hipGetLastError()) != hipSuccess) break;
+    }
+    if (e != hipSuccess) break;
+    if ((e = hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, st)) != hipSuccess) break;
+    e = hipStreamSynchronize(st);
+  } while (false);
+  hipFree(buf);
+  if (e != hipSuccess) return e;
+  const int nsteps = kBR + kc - 1;
+  out4[0] = 10.0 * (double)h[0] / ((double)blocks * nsteps);
+  out4[1] = 10.0 * (double)h[0] / (double)blocks;
+  out4[2] = 10.0 * (double)h[2] / (2.0 * rounds);
+  out4[3] = 10.0 * (double)h[4] / (2.0 * rounds);
+  *timed_out = (h[3] != 0 || h[5] != 0) ? 1 : 0;
+  return hipSuccess;
 }
 
 }  // namespace chm

@@ -132,8 +132,9 @@ def test_batched_workspace_and_validation(nat):
 def test_server_bad_config_rejected_on_host(nat):
     lib = nat.load()
     out = ctypes.c_void_p()
-    for cfg in [nat.ServerCfg(16, 0, 0), nat.ServerCfg(1 << 20, -1, 0),
-                nat.ServerCfg(1 << 20, 70000, 0)]:
+    for cfg in [nat.ServerCfg(16, 0, 0, 0, 0), nat.ServerCfg(1 << 20, -1, 0, 0, 0),
+                nat.ServerCfg(1 << 20, 70000, 0, 0, 0), nat.ServerCfg(1 << 20, 0, 0, -1, 0),
+                nat.ServerCfg(1 << 20, 0, 0, 17, 0)]:
         assert lib.cholmod_server_create(ctypes.byref(cfg), ctypes.byref(out)) == nat.ERR_ARG
     assert lib.cholmod_server_create(None, ctypes.byref(out)) == nat.ERR_ARG
     assert lib.cholmod_server_add_factor(None, FAKE, 4, 4, 0, None) == nat.ERR_ARG

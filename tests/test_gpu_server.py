@@ -75,8 +75,8 @@ def test_server_reports_failures_per_request(orc):
     L2, V2 = problem(200, 16, seed=72)
     big = torch.zeros(5000, 5000, dtype=torch.float64, device="cuda")
     big.diagonal().fill_(1.0)
-    # 1 MiB slots: the two small requests fit together; the n = 5000, k = 16
-    # request needs about 3.3 MB of workspace and can never run
+    # a 1 MiB budget: the two small requests fit together; the n = 5000,
+    # k = 16 request needs about 3.3 MB of workspace and can never run
     with chm.Server(ws_bytes=1 << 20, max_batch=4) as srv:
         a = srv.add_factor(dev(L, False))
         b = srv.add_factor(dev(L2, False))
@@ -88,7 +88,7 @@ def test_server_reports_failures_per_request(orc):
         s1, s2, s3 = srv.poll(t1), srv.poll(t2), srv.poll(t3)
     assert s1[0] == chm.ERR_NOT_PD
     assert s2[0] == 0
-    assert s3[0] == chm.ERR_ARG  # needs more workspace than one batch slot has
+    assert s3[0] == chm.ERR_ARG  # its workspace exceeds the server's whole HBM budget
 
 
 def test_server_rejects_overflowing_sizes():
@@ -115,3 +115,55 @@ def test_server_rejects_overflowing_sizes():
         assert srv.poll(ok)[0] == 0
     # V = 0 leaves the identity factor unchanged
     assert torch.allclose(L, torch.eye(100, dtype=torch.float64, device="cuda"), atol=1e-15)
+
+
+def test_server_batches_overlap_on_the_device(orc):
+    """Requests that arrive while a long batch runs are launched at once on
+    another stream and finish while it is still running; each result equals
+    the same request applied alone (bit for bit) and the oracle's."""
+    import time
+    import paper_1011_1173_amd as chm
+    from gpu_util import inputs
+    print_case("server-overlap")
+    nbig, ksmall = 16384, 4
+    Lbig = inputs.spd_factor(nbig, 91, device="cuda")
+    Vbig = inputs.update_vectors(nbig, 32, 91, device="cuda")
+    smalls = [problem(300 + 17 * i, ksmall, 920 + i) for i in range(4)]
+    alone = []
+    for L, V in smalls:
+        Ld, Vd = dev(L, False), dev(V, False)
+        st, _, _ = chm.update_async(Ld, Vd, +1).status()
+        assert st == 0
+        alone.append(Ld.cpu().numpy())
+    Ls = [dev(L, False) for L, _ in smalls]
+    Vs = [dev(V, False) for _, V in smalls]
+    torch.cuda.synchronize()
+    with chm.Server(ws_bytes=1 << 30, max_batch=16, streams=4) as srv:
+        big = srv.add_factor(Lbig)
+        ids = [srv.add_factor(L) for L in Ls]
+        tb = srv.submit(big, Vbig, +1)
+        time.sleep(0.002)  # the big batch is on the GPU
+        ts = [srv.submit(i, V, +1) for i, V in zip(ids, Vs)]
+        small_res, big_done_first = [], False
+        for t in ts:
+            while True:
+                r = srv.poll(t)
+                if r is not None:
+                    break
+                time.sleep(2e-5)
+            small_res.append(r)
+        # every small request is done: the big one must still be running
+        rb = srv.poll(tb)
+        big_done_first = rb is not None
+        srv.drain()
+        if rb is None:
+            rb = srv.poll(tb)
+    assert all(r[0] == 0 for r in small_res) and rb[0] == 0
+    assert not big_done_first, "the small requests waited for the long batch"
+    lat_small = max(r[1] for r in small_res)
+    assert lat_small < rb[1], (lat_small, rb[1])
+    for f, (L, V) in enumerate(smalls):
+        out = Ls[f].cpu().numpy()
+        assert np.array_equal(out, alone[f]), "factor %d differs from its result alone" % f
+        ref, st, _ = orc.modify(L, V, +1)
+        assert st == 0 and rel_diff(out, ref) <= RESID_TOL
