@@ -125,7 +125,8 @@ struct SbLds {
   int fail;                 // first failing (row * 16 + column) of the block
   int tk;                   // owner schedule: this workgroup's ticket
   int tmo;                  // owner schedule: a wait ran out of time
-  int up[2];                // owner schedule: rows of the applied block staged, by round parity
+  int cnt[2][4];            // owner schedule: rows of each 16-row window of the applied
+                            // block staged, by round parity
 };
 
 // Row shift by D lanes within each 16-lane row (DPP row_shr:D); the first D
@@ -313,7 +314,9 @@ __device__ __forceinline__ void sub2x2(const ST* tile_in, ST* tile, const RotRec
   // s + 1 <= 71: record rows up to 87
   qn[0] = rp[(s + 1) * kKP];
   qn[1] = rp[(s + 1) * kKP + 1];
-  if (h == 0) {
+  {
+    // only lanes h = 0 use it; the others read the same address (one LDS
+    // broadcast per column pair), which costs less than masking them off
     const int rn2 = imin(s + 2, kBR - 1);
 #pragma unroll
     for (int u = 0; u < 2; ++u) fn[u] = (ST)tile_in[rn2 * LD + c0 + u];
@@ -919,18 +922,23 @@ __device__ __forceinline__ void block_work(SbLds& sh, ST* __restrict__ L, ST* __
 constexpr int64_t kWaitTicks = 500000000;  // steady-counter ticks (5 s at 100 MHz)
 
 // The owner's apply runs on waves 0-3 (one per SIMD) with the two-rotation,
-// two-column lanes of sub2x2.  Wave 4 fetches the records: it waits until a prefix of the next 16 rows
-// has been published, stages those rows in sh.R and announces how far the
-// staged rows go (sh.up, by round parity); the apply waves then run the
-// sub-steps whose rows are all staged, while wave 4 fetches the next rows.
-// Waves 5-7 only pass the rounds' barriers.
+// two-column lanes of sub2x2.  Waves 4-7 fetch the records: wave 4 + w
+// polls the records of rows [16 w, 16 w + 16) of the applied block, stages
+// those that have been published in sh.R and counts how many rows of its
+// window (a prefix) are staged.  In rounds separated by barriers, the apply
+// waves run the sub-steps whose rows are all staged -- the rows before the
+// first window that is not complete -- while the fetch waves stage more.
+// Only the wave whose window is the first incomplete one waits for records
+// to appear; a block whose records are all published (an owner far behind
+// the chain) is staged in one round and applied without a barrier.
 
 // Apply block [pb, pb + 64) (tile staged in sh.A, the caller has
 // synchronised) to the owner's columns; w: an apply lane's V values.  next:
 // block pb is the one just before the owner's own (its chain waits for this
-// apply), so wave 4 polls without delay; the owners further right poll
-// slowly, which keeps their reads of the same few records from crowding the
-// memory channels.  Same operations, in the same order, as apply2x2.
+// apply), so the waiting fetch wave polls without delay; the owners further
+// right poll slowly, which keeps their reads of the same few records from
+// crowding the memory channels.  Same operations, in the same order, as
+// apply2x2.
 template <int SG, typename ST, int KCF>
 __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
                                             ST (&w)[kOwnCols],
@@ -941,6 +949,17 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
   const int kc = KCF ? KCF : kc_;
   const int tid = threadIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  // rows staged before the first incomplete window, from the round's counts
+  auto staged_prefix = [&](int par) {
+    int up = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = sh.cnt[par][q];
+      up += c;
+      if (c < 16) break;
+    }
+    return up;
+  };
   if (wv < 4) {
     const int h = (lane & 15) >> 1;
     const int c0 = own_col(tid, 0);
@@ -960,7 +979,7 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
     int s = 0;
     for (int rd = 0;; ++rd) {
       __syncthreads();
-      const int up = sh.up[rd & 1];
+      const int up = staged_prefix(rd & 1);
       const int lim = up >= kBR ? S : up;  // rows <= s - h < up are staged
       RotRec qa[2] = {rp[s * kKP], rp[s * kKP + 1]}, qb[2];
       for (; s + 2 <= lim; s += 2) {
@@ -975,15 +994,17 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
       }
       if (up >= kBR) break;
     }
-  } else if (wv == 4) {
-    // lane holds rows up + 4 v + lane / 16 (v = 0..3) of the window, column m
+  } else {
+    // fetch wave q: rows r0 + up_w + 4 v + lane / 16 (v = 0..3) of its
+    // window [r0, r0 + 16), column m
+    const int q = wv - 4, r0 = 16 * q;
     const int m = lane & 15, rl = lane >> 4;
     U f[4][3];
-    auto fetch = [&](int up) {
+    auto fetch = [&](int upw) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = up + 4 * v + rl;
-        if (r < kBR && m < kc) {
+        const int r = r0 + upw + 4 * v + rl;
+        if (upw + 4 * v + rl < 16 && r < kBR && m < kc) {
           const GRec<ST>* src = T + (pb + r) * kKP + m;
           f[v][0] = load_bits(&src->c);
           f[v][1] = load_bits(&src->s);
@@ -993,7 +1014,7 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
         }
       }
     };
-    // rows of the window (bit 4 v + group) whose records are all there
+    // rows of the window's rest (bit 4 v + group) whose records are all there
     auto ready_rows = [&]() {
       uint32_t full = 0;
 #pragma unroll
@@ -1006,44 +1027,45 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
       }
       return full;
     };
-    int up = 0;
+    int upw = 0;          // rows of the window staged
+    int known = 0;        // rows of the block staged before the first incomplete window
     fetch(0);
     for (int rd = 0;; ++rd) {
-      int nr = __builtin_ctz(~ready_rows());
-      while (nr == 0) {
-        if (wall_clock64() > deadline) {  // give up: stage what is there
-          sh.tmo = 1;
-          nr = 16;
-          break;
+      if (upw < 16) {
+        int nr = __builtin_ctz(~ready_rows());
+        // the first incomplete window waits for at least one more row
+        while (nr == 0 && known == r0 + upw) {
+          if (wall_clock64() > deadline) {  // give up: stage what is there
+            sh.tmo = 1;
+            nr = 16;
+            break;
+          }
+          if (next) __builtin_amdgcn_s_sleep(1);
+          else __builtin_amdgcn_s_sleep(100);
+          fetch(upw);
+          nr = __builtin_ctz(~ready_rows());
         }
-        if (next) __builtin_amdgcn_s_sleep(1);
-        else __builtin_amdgcn_s_sleep(100);
-        fetch(up);
-        nr = __builtin_ctz(~ready_rows());
-      }
-      if (nr > kBR - up) nr = kBR - up;
+        if (sh.tmo) nr = 16;  // a wait ran out: every window counts as staged
+        if (nr > 16 - upw) nr = 16 - upw;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = up + 4 * v + rl;
-        if (4 * v + rl < nr && m < kc) {
-          RotRec rec;
-          rec.c = (double)__builtin_bit_cast(ST, f[v][0]);
-          rec.s = (double)__builtin_bit_cast(ST, f[v][1]);
-          rec.ic = (double)__builtin_bit_cast(ST, f[v][2]);
-          rec.ss = 0.0;
-          sh.R[kPad + r][m] = rec;
+        for (int v = 0; v < 4; ++v) {
+          const int rr = upw + 4 * v + rl, r = r0 + rr;
+          if (4 * v + rl < nr && r < kBR && m < kc) {
+            RotRec rec;
+            rec.c = (double)__builtin_bit_cast(ST, f[v][0]);
+            rec.s = (double)__builtin_bit_cast(ST, f[v][1]);
+            rec.ic = (double)__builtin_bit_cast(ST, f[v][2]);
+            rec.ss = 0.0;
+            sh.R[kPad + r][m] = rec;
+          }
         }
+        upw += nr;
+        if (upw < 16) fetch(upw);  // in flight while the apply waves run
       }
-      up += nr;
-      if (lane == 0) sh.up[rd & 1] = up;
-      if (up < kBR) fetch(up);  // in flight while the apply waves run
+      if (lane == 0) sh.cnt[rd & 1][q] = upw;
       __syncthreads();
-      if (up >= kBR) break;
-    }
-  } else {
-    for (int rd = 0;; ++rd) {
-      __syncthreads();
-      if (sh.up[rd & 1] >= kBR) break;
+      known = staged_prefix(rd & 1);
+      if (known >= kBR) break;
     }
   }
 }
