@@ -47,9 +47,13 @@ static int check_args(const double *L, const double *V, int64_t n, int64_t k,
 }
 
 /*
- * Compute (Algorithm 1, helper "Compute"):
- *   w = sqrt(L_ii^2 + sigma V_i^2);  c = w / L_ii;  s = V_i / L_ii;  L_ii = w
- * All three outputs use the OLD diagonal.  Returns a status.
+ * The rotation of row i against one column of the work copy of V (the
+ * "Compute" step of Algorithm 1).  Adding sigma v v^T to a factor whose
+ * leading entry is l changes that entry to w, the positive root of
+ * w^2 = l^2 + sigma v^2; the pair (c, s) = (w, v) / l is the rotation that
+ * Apply then carries along the row.  c and s are both taken relative to
+ * the diagonal as it was BEFORE this column, and the diagonal is replaced
+ * by w last.  Returns a status.
  * Failure readings (the paper is silent): an input diagonal that is not
  * > 0 is a bad factor (-3); a radicand that is not > 0 (negative, zero or
  * NaN) means A + sigma V V^T is not positive definite (-2).
@@ -67,9 +71,11 @@ static int compute_rot(double *Lii, double v, double sg, double *c, double *s) {
 }
 
 /*
- * Apply (Algorithm 1, helper "Apply"):
- *   L_ij = (L_ij + sigma s V_j) / c;   V_j = c V_j - s L_ij
- * The second statement uses the NEW L_ij (the statements are sequential).
+ * One rotation applied to an off-diagonal pair (L_ij, V_j) (the "Apply"
+ * step of Algorithm 1): the row entry becomes its sum with sigma s V_j,
+ * divided by c; the V entry becomes c V_j minus s times the row entry just
+ * computed -- the updated row entry, not the old one, which is what keeps
+ * the hyperbolic rotation stable for downdates.
  */
 static void apply_rot(double c, double s, double sg, double *Lij, double *Vj) {
     const double lij = (*Lij + sg * (s * *Vj)) / c;
