@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
-PROFILE = os.path.join(ROOT, "profiles", "k_sb_owner_n5000_k16.md")
+PROFILE = os.path.join(ROOT, "profiles", "k_sb_queue_n5000_k16.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1011_1173_amd", "csrc", "sysblk.hip")
 
 
@@ -47,13 +47,14 @@ def measured_traffic():
 
 def critical_path(chm, n, k, passes, mean_ms, alg_bytes):
     """The serial floor of one factor: the rows form a chain (a row's Compute
-    needs V after the Apply of every earlier row), run block by block.  The
-    library's latency probe measures a 64-row block's chain alone (in LDS)
-    and the hand-off between workgroups; T_crit = blocks x passes x (chain
-    of a block), which no schedule of this blocking can beat, against the
-    HBM time of the algorithmic bytes."""
-    nb = ((n + 63) // 64) * passes
-    out = {"blocks_x_passes": nb, "us_per_block": mean_ms * 1e3 / nb}
+    needs V after the Apply of every earlier row), run block by block; the
+    16-column passes of V follow each other one block apart.  The library's
+    latency probe measures a 64-row block's chain alone (in LDS) and the
+    hand-off between workgroups; T_crit = (blocks + passes - 1) x (chain of
+    a block), which no schedule of this blocking can beat, against the HBM
+    time of the algorithmic bytes."""
+    nb = (n + 63) // 64 + passes - 1
+    out = {"blocks_on_chain": nb, "us_per_block": mean_ms * 1e3 / nb}
     try:
         step_ns, block_ns, hand_x_ns, hand_s_ns = chm._native.probe_latency(
             k=min(k, 16), blocks=200, rounds=2000)
@@ -78,6 +79,8 @@ def parse():
     ap.add_argument("--n", type=int, default=5000)
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-served", action="store_true",
+                    help="headline mode: skip the served-latency part of the metric")
     ap.add_argument("--mode", choices=["headline", "batched", "served", "sweep", "ooc"],
                     default="headline",
                     help="headline: one factor, n=5000, k=16 (default); batched: 256 factors "
@@ -87,8 +90,8 @@ def parse():
                          "factors in host memory streamed in 64-row panels (n in {5e3, 2e4})")
     ap.add_argument("--batch-dtype", choices=["f64", "f32s"], default="f64",
                     help="batched mode: storage type of the factors")
-    ap.add_argument("--served-seconds", type=float, default=3.0,
-                    help="served mode: arrival window per load level")
+    ap.add_argument("--served-seconds", type=float, default=2.0,
+                    help="served workload: arrival window per load level")
     ap.add_argument("--served-factors", type=int, default=64)
     ap.add_argument("--served-max-n", type=int, default=16384)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -399,12 +402,26 @@ def ooc(args):
 
 
 def served(args):
+    """--mode served: the served workload alone, as its own JSON line."""
+    res = served_run(args, args.served_seconds)
+    out = {"metric": "served p50/p99 latency (update + downdate of the oldest V per request)",
+           "value": res["levels"][-1]["p99_ms"], "unit": "ms (p99 at 90% load)", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": res["workload"], "dense_GB": res["dense_GB"]},
+           "saturated_pairs_per_s": res["saturated_pairs_per_s"], "levels": res["levels"]}
+    print(json.dumps(out))
+    return 0
+
+
+def served_run(args, seconds):
     """Served workload: a pool of factors with sizes cycled over {1024, 2048,
     4096, 8192, 16384}, each with 4 prior V's already added (untimed).  A
     request is an update of one factor by a new V (k ~ U{1..32}, N(0,1)/sqrt(n))
     followed by the downdate of that factor's oldest added V; its latency runs
     from its arrival to the completion of both.  Saturated throughput is
-    measured with a burst; then Poisson arrivals at 25/50/75/90% of it."""
+    measured with a burst; then Poisson arrivals at 25/50/75/90% of it, each
+    for `seconds`.  The server admits requests against a 6 GiB HBM budget
+    and keeps up to 4 batches in flight."""
     import random
     import torch
     import paper_1011_1173_amd as chm
@@ -439,7 +456,7 @@ def served(args):
     torch.cuda.synchronize()
     print("served: prior V's added", file=sys.stderr, flush=True)
     dense_gb = sum(8.0 * L.shape[0] * L.shape[1] for L in factors) / 1e9
-    srv = chm.Server(ws_bytes=6 << 30, max_batch=nf)
+    srv = chm.Server(ws_bytes=6 << 30, max_batch=nf, streams=4)
     ids = [srv.add_factor(L) for L in factors]
     req_bytes = []
 
@@ -495,7 +512,7 @@ def served(args):
         req_bytes.clear()
         while True:
             t_next += rng.expovariate(rate)
-            if t_next - t_start > args.served_seconds:
+            if t_next - t_start > seconds:
                 break
             while time.perf_counter() < t_next:
                 pass
@@ -515,15 +532,13 @@ def served(args):
                        "p99_ms": 1e3 * lat[min(cnt - 1, int(0.99 * cnt))] if cnt else None,
                        "effective_GBps": sum(req_bytes) / span / 1e9})
     srv.close()
-    out = {"metric": "served p50/p99 latency (update + downdate of the oldest V per request)",
-           "value": levels[-1]["p99_ms"], "unit": "ms (p99 at 90% load)", "n_gpus": 1,
-           "higher_is_better": False, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "served pool: %d factors, n cycled over %s, 4 prior V's each, "
-                                  "k ~ U{1..32}, Poisson arrivals" % (nf, sizes),
-                      "dense_GB": dense_gb},
-           "saturated_pairs_per_s": sat_rate, "levels": levels}
-    print(json.dumps(out))
-    return 0
+    del factors, windows
+    torch.cuda.empty_cache()
+    return {"workload": "served pool: %d factors, n cycled over %s, 4 prior V's each, "
+                        "k ~ U{1..32}, Poisson arrivals, %.1f s per load level"
+                        % (nf, sizes, seconds),
+            "dense_GB": dense_gb, "saturated_pairs_per_s": sat_rate,
+            "saturated_updates_per_s": 2.0 * sat_rate, "levels": levels}
 
 
 def main():
@@ -616,16 +631,15 @@ def main():
     mean = sum(per) / len(per)
     alg_bytes = 8.0 * n * (n + 1) + 8.0 * n * k
     ms_per_step = total_ms / K
-    # Dominant kernel: the owner launch of the fast schedule, one per
-    # 16-column pass of V.  A modification is a preparation launch (W <- V),
-    # then per pass a clear launch (empty records) and the owner launch, back
-    # to back on `stream`; the events above bracket all of them, so the
-    # owner launch's duration is taken as the modification time over the
-    # passes (the two small launches included: a conservative figure).
+    # Dominant kernel: the persistent owner launch of the fast schedule, one
+    # per modification (all 16-column passes of V).  A modification is a
+    # preparation launch (W <- V), a clear launch (empty records) and the
+    # owner launch, back to back on `stream`; the events above bracket all
+    # three, so the owner launch's duration is taken as the modification time
+    # (the two small launches included: a conservative figure).
     passes = (k + 15) // 16
-    launches = passes
-    avg_launch_us = mean * 1e3 / launches
-    bytes_per_launch = alg_bytes / passes
+    avg_launch_us = mean * 1e3
+    bytes_per_launch = alg_bytes
     achieved = bytes_per_launch / (avg_launch_us * 1e-6) / 1e9
     out = {
         "metric": "updates/s + effective HBM GB/s (n=5000,k=16); served p50/p99 latency",
@@ -645,13 +659,11 @@ def main():
                      "measured_copy_GBps": copy_gbs,
                      "frac_of_measured_copy": achieved / copy_gbs,
                      "cold_mall": {"median_ms": cold_med,
-                                   "achieved_GBps": bytes_per_launch / (cold_med * 1e-3 / passes)
-                                   / 1e9,
+                                   "achieved_GBps": bytes_per_launch / (cold_med * 1e-3) / 1e9,
                                    "what": "512 MB written before each timed modification"},
                      "traffic": measured_traffic() if (n, k) == (5000, 16) else None,
-                     "kernel": "k_sb_owner (one launch per 16-column pass)",
-                     "launches_per_modification": {"dominant_kernel": passes,
-                                                   "all": 1 + 2 * passes},
+                     "kernel": "k_sb_queue (one persistent launch per modification)",
+                     "launches_per_modification": {"dominant_kernel": 1, "all": 3},
                      "avg_launch_us": avg_launch_us,
                      "alg_bytes_per_launch": bytes_per_launch},
         # the single-factor path is bound by its serial chain of blocks, not by
@@ -661,6 +673,12 @@ def main():
         "round_trip_drift": drift,
         "wall_s": wall,
     }
+    if not args.no_served:
+        # the served half of the metric: p50/p99 latency on the served pool
+        L0, V = L0.cpu(), V.cpu()  # the CPU baseline's inputs
+        del L, ws
+        torch.cuda.empty_cache()
+        out["served"] = served_run(args, args.served_seconds)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(L0, V)
     print(json.dumps(out))
