@@ -210,11 +210,66 @@ typedef struct cholmod_desc {
   int32_t dtype;    /* CHOLMOD_F64 or CHOLMOD_F32S */
 } cholmod_desc;
 
-/* Workspace bytes of a batch (0 if any descriptor is invalid). */
+/* Workspace bytes of a batch under any launch plan (0 if any descriptor is
+ * invalid). */
 size_t cholmod_workspace_bytes_batched(const cholmod_desc *descs, int64_t count);
 
 int cholmod_update_batched(const cholmod_desc *descs, int64_t count, void *ws, size_t ws_bytes,
                            int64_t *d_info, cholmod_stream_t stream);
+
+/*
+ * Launch plans of batches.  A batch runs under one of two schedules, the
+ * same per-element operations either way (every result is bit for bit the
+ * single-factor one):
+ *   CHOLMOD_SCHED_QUEUED   one preparation launch and one persistent launch
+ *                          whose workgroups take owner items (the columns
+ *                          of block j of factor f, every 16-column pass)
+ *                          from a counter;
+ *   CHOLMOD_SCHED_STEPPED  one preparation launch and one launch per block
+ *                          step (block b of every factor that has one).
+ * The queued launch has `grid` workgroups (0 = one per compute unit), takes
+ * the items block-major (all factors' block 0, then block 1, ...) or
+ * factor-major (every block of the longest factor, then the next), and
+ * owners far from the chain sleep 64 x {1, 20, 100} cycles between polls
+ * (poll = 0, 1, 2).
+ * cholmod_update_batched takes the plan from a table indexed by the batch's
+ * dominant (storage type, n bucket, k bucket) -- the bucket with most of
+ * the batch's work, n^2 k summed over its factors; n buckets end at 256,
+ * 1024, 4096, 16384 (bucket 4: larger), k buckets at 16, 32, 64 (bucket 3:
+ * larger).  The table starts with {QUEUED, 0, BLOCK, 2} everywhere and is
+ * filled by cholmod_set_plan, normally from the plan cache of the
+ * library's autotuner (paper_1011_1173_amd/tune.py), which times the
+ * candidate plans of each bucket on the GPU.  The served mode uses the
+ * table's grid, order and poll with the queued schedule.
+ */
+#define CHOLMOD_SCHED_QUEUED 0
+#define CHOLMOD_SCHED_STEPPED 1
+#define CHOLMOD_ORDER_BLOCK 0
+#define CHOLMOD_ORDER_FACTOR 1
+
+typedef struct cholmod_plan {
+  int32_t schedule;  /* CHOLMOD_SCHED_* */
+  int32_t grid;      /* queued: persistent workgroups, 0 = one per compute unit (<= 65536) */
+  int32_t order;     /* queued: CHOLMOD_ORDER_* */
+  int32_t poll;      /* queued: 0, 1 or 2 */
+} cholmod_plan;
+
+/* cholmod_update_batched with an explicit plan (NULL: the table's plan).
+ * CHOLMOD_ERR_ARG for an invalid plan, otherwise as cholmod_update_batched. */
+int cholmod_update_batched_plan(const cholmod_desc *descs, int64_t count,
+                                const cholmod_plan *plan, void *ws, size_t ws_bytes,
+                                int64_t *d_info, cholmod_stream_t stream);
+
+/* Plan table entries (thread-safe; CHOLMOD_ERR_ARG for a bad index or plan). */
+int cholmod_set_plan(int dtype, int n_bucket, int k_bucket, const cholmod_plan *plan);
+int cholmod_get_plan(int dtype, int n_bucket, int k_bucket, cholmod_plan *plan);
+
+/* The table buckets of a factor of size n with k columns of V. */
+int cholmod_plan_bucket(int64_t n, int64_t k, int *n_bucket, int *k_bucket);
+
+/* Compute units of the current device (0 on error): the grid of a full
+ * queued launch. */
+int cholmod_compute_units(void);
 
 /*
  * A batch captured once as a HIP graph and replayed: for a fixed set of

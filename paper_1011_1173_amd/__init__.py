@@ -18,7 +18,7 @@ from . import _native
 from ._native import (ERR_ARG, ERR_BAD_DIAG, ERR_HIP, ERR_NOT_PD, F32S, F64, FLAG_BLOCKED,
                       FLAG_EXACT, INFO_NONE, OK, LibraryMissing)
 
-__all__ = ["update", "update_async", "update_batched", "update_batched_async",
+__all__ = ["update", "update_async", "update_batched", "update_batched_async", "load_plans",
            "update_ooc", "workspace_bytes", "workspace_bytes_ooc", "BatchGraph", "CholmodError", "ArgumentError", "NotPositiveDefinite",
            "BadDiagonal", "HipError", "LibraryMissing", "Pending", "PendingBatch", "Server"]
 
@@ -232,16 +232,32 @@ def _descs(Ls, Vs, sigmas):
     return arr, ks, dev
 
 
+_plans_loaded = False
+
+
+def _ensure_plans():
+    """Load the shipped plan cache into the library once (before the first
+    batched call); without a cache the library's default plan applies."""
+    global _plans_loaded
+    if not _plans_loaded:
+        _plans_loaded = True
+        from . import tune
+        tune.load_plans()
+
+
 def update_batched_async(Ls, Vs, sigmas, *, stream=None, workspace: torch.Tensor | None = None,
-                         info: torch.Tensor | None = None) -> PendingBatch:
+                         info: torch.Tensor | None = None, plan=None) -> PendingBatch:
     """Enqueue the modification of every factor Ls[i] by (Vs[i], sigmas[i])
-    (cholmod_update_batched); float64 and float32 factors may be mixed."""
+    (cholmod_update_batched); float64 and float32 factors may be mixed.
+    ``plan``: a launch plan (dict with schedule, grid, order, poll, or a
+    _native.Plan) instead of the library's plan table."""
     arr, ks, dev = _descs(Ls, Vs, sigmas)
     count = len(ks)
     if count == 0:
         raise ArgumentError("empty batch")
     stream = torch.cuda.current_stream(dev) if stream is None else stream
     lib = _native.load()
+    _ensure_plans()
     need = int(lib.cholmod_workspace_bytes_batched(arr, count))
     if need == 0:
         raise ArgumentError("invalid batch")
@@ -249,18 +265,23 @@ def update_batched_async(Ls, Vs, sigmas, *, stream=None, workspace: torch.Tensor
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
     if info is None:
         info = torch.empty(count, dtype=torch.int64, device=dev)
-    st = lib.cholmod_update_batched(arr, count, ctypes.c_void_p(workspace.data_ptr()),
-                                    workspace.numel(), ctypes.c_void_p(info.data_ptr()),
-                                    _stream_handle(stream))
+    if plan is not None and not isinstance(plan, _native.Plan):
+        plan = _native.Plan(int(plan.get("schedule", 0)), int(plan.get("grid", 0)),
+                            int(plan.get("order", 0)), int(plan.get("poll", 2)))
+    st = lib.cholmod_update_batched_plan(arr, count,
+                                         ctypes.byref(plan) if plan is not None else None,
+                                         ctypes.c_void_p(workspace.data_ptr()),
+                                         workspace.numel(), ctypes.c_void_p(info.data_ptr()),
+                                         _stream_handle(stream))
     _raise_for(st)
     return PendingBatch(ks, workspace, info, stream)
 
 
-def update_batched(Ls, Vs, sigmas, *, stream=None):
+def update_batched(Ls, Vs, sigmas, *, stream=None, plan=None):
     """Modify every factor and wait; returns [(status, row, col)] per factor
     (a numerical failure in one factor does not raise and does not affect
     the others)."""
-    return update_batched_async(Ls, Vs, sigmas, stream=stream).statuses()
+    return update_batched_async(Ls, Vs, sigmas, stream=stream, plan=plan).statuses()
 
 
 class BatchGraph:
@@ -275,6 +296,7 @@ class BatchGraph:
         if count == 0:
             raise ArgumentError("empty batch")
         lib = _native.load()
+        _ensure_plans()
         need = int(lib.cholmod_workspace_bytes_batched(arr, count))
         if need == 0:
             raise ArgumentError("invalid batch")
@@ -326,6 +348,7 @@ class Server:
     def __init__(self, ws_bytes: int = 1 << 30, max_batch: int = 256, device=None,
                  streams: int = 4):
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        _ensure_plans()
         cfg = _native.ServerCfg(int(ws_bytes), int(max_batch), int(dev.index), int(streams), 0)
         h = ctypes.c_void_p()
         _raise_for(_native.load().cholmod_server_create(ctypes.byref(cfg), ctypes.byref(h)))
@@ -386,3 +409,11 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def load_plans(path: str | None = None) -> int:
+    """Fill the library's plan table from an autotuner plan cache (JSON, see
+    tune.py); default: the cache shipped for this GPU architecture, if any.
+    Returns the number of entries set."""
+    from . import tune
+    return tune.load_plans(path)

@@ -27,7 +27,13 @@ EXPORTS = (
     "cholmod_server_create", "cholmod_server_add_factor", "cholmod_server_submit",
     "cholmod_server_poll", "cholmod_server_drain", "cholmod_server_destroy",
     "cholmod_noalloc_max_bytes", "cholmod_update_noalloc", "cholmod_probe_latency",
+    "cholmod_update_batched_plan", "cholmod_set_plan", "cholmod_get_plan", "cholmod_plan_bucket",
+    "cholmod_compute_units",
 )
+
+SCHED_QUEUED, SCHED_STEPPED = 0, 1
+ORDER_BLOCK, ORDER_FACTOR = 0, 1
+N_BUCKETS, K_BUCKETS = 5, 4
 
 
 class ServerCfg(ctypes.Structure):
@@ -35,6 +41,12 @@ class ServerCfg(ctypes.Structure):
     _fields_ = [("ws_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("streams", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class Plan(ctypes.Structure):
+    """struct cholmod_plan of the header."""
+    _fields_ = [("schedule", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("poll", ctypes.c_int32)]
 
 
 class Desc(ctypes.Structure):
@@ -100,6 +112,17 @@ def load():
     lib.cholmod_batch_graph_destroy.argtypes = [p]
     lib.cholmod_batch_graph_destroy.restype = ci
     lib.cholmod_update_batched.restype = ci
+    pp = ctypes.POINTER(Plan)
+    lib.cholmod_update_batched_plan.argtypes = [dp, i64, pp, p, sz, p, p]
+    lib.cholmod_update_batched_plan.restype = ci
+    lib.cholmod_set_plan.argtypes = [ci, ci, ci, pp]
+    lib.cholmod_set_plan.restype = ci
+    lib.cholmod_get_plan.argtypes = [ci, ci, ci, pp]
+    lib.cholmod_get_plan.restype = ci
+    lib.cholmod_plan_bucket.argtypes = [i64, i64, ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    lib.cholmod_plan_bucket.restype = ci
+    lib.cholmod_compute_units.argtypes = []
+    lib.cholmod_compute_units.restype = ci
     lib.cholmod_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(p)]
     lib.cholmod_server_create.restype = ci
     lib.cholmod_server_add_factor.argtypes = [p, p, i64, i64, ci, ctypes.POINTER(ctypes.c_int32)]

@@ -34,7 +34,9 @@ hipError_t run_probe_latency(hipStream_t st, int kc, int blocks, int rounds, dou
 hipError_t run_sysblk_batch_step(hipStream_t st, const BatchFactor* d_fac,
                                  const BatchEntry* d_ent, const BatchStep& S);
 hipError_t run_sysblk_qbatch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
-                             const QItem* d_items, int64_t nitems, int32_t* d_ticket);
+                             const QItem* d_items, int64_t nitems, int32_t* d_ticket, int grid,
+                             int poll);
+int compute_units();
 
 namespace {
 
@@ -255,6 +257,7 @@ constexpr int64_t kBlock = 64, kPass = 16, kMaxBatch = 65535;
 // [factors][entries].
 struct BatchPlan {
   bool queued = true;
+  int grid = 0, poll = 2;  // queued launch: persistent workgroups (0 = one per CU), poll level
   std::vector<BatchFactor> fac;
   std::vector<BatchEntry> ent;
   std::vector<BatchStep> steps;
@@ -275,7 +278,7 @@ int validate_desc(const cholmod_desc& d) {
 // the same operations in the same order), so every factor's result is the
 // one it gets alone.
 int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P,
-               bool queued = true) {
+               bool queued = true, int order = CHOLMOD_ORDER_BLOCK) {
   if (count < 0 || count > kMaxBatch) return CHOLMOD_ERR_ARG;
   if (count > 0 && descs == nullptr) return CHOLMOD_ERR_ARG;
   P->queued = queued;
@@ -336,23 +339,31 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P,
     F.dtype = d.dtype == CHOLMOD_F64 ? kStoreF64 : kStoreF32;
   }
   // longest factor first; at step s the active factors are a prefix
-  std::vector<int64_t> order(count);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
+  std::vector<int64_t> order_of(count);
+  std::iota(order_of.begin(), order_of.end(), 0);
+  std::stable_sort(order_of.begin(), order_of.end(),
                    [&](int64_t a, int64_t b) { return steps[a] > steps[b]; });
   if (queued) {
-    // by block index, longest factor first within a block index: an item
-    // waits only for its factor's items of lower blocks, which come earlier
+    // block-major: by block index, longest factor first within a block
+    // index; factor-major: every block of the longest factor, then of the
+    // next.  Either way an item waits only for its factor's items of lower
+    // blocks, which come earlier.
     P->items.clear();
     P->items.reserve(total_items);
-    for (int64_t b = 0; b < bmax; ++b)
-      for (int64_t f : order) {
-        if (b >= blocks[f]) continue;
-        QItem it;
-        it.f = (int32_t)f;
-        it.j = (int32_t)b;
-        P->items.push_back(it);
-      }
+    auto push = [&](int64_t f, int64_t b) {
+      QItem it;
+      it.f = (int32_t)f;
+      it.j = (int32_t)b;
+      P->items.push_back(it);
+    };
+    if (order == CHOLMOD_ORDER_FACTOR) {
+      for (int64_t f : order_of) 
+        for (int64_t b = 0; b < blocks[f]; ++b) push(f, b);
+    } else {
+      for (int64_t b = 0; b < bmax; ++b)
+        for (int64_t f : order_of)
+          if (b < blocks[f]) push(f, b);
+    }
     return CHOLMOD_OK;
   }
   P->ent.clear();
@@ -362,7 +373,7 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P,
     BatchStep& S = P->steps[s];
     S.off = (int64_t)P->ent.size();
     int64_t rest = 0;
-    for (int64_t f : order) {
+    for (int64_t f : order_of) {
       if (s >= steps[f]) break;
       const cholmod_desc& d = descs[f];
       const int64_t pass = s / blocks[f], b = s % blocks[f];
@@ -400,6 +411,13 @@ size_t batch_workspace_bytes(const cholmod_desc* descs, int64_t count, bool queu
   return P.total;
 }
 
+// Workspace that fits a batch under either schedule.
+size_t batch_workspace_bytes_any(const cholmod_desc* descs, int64_t count) {
+  const size_t a = batch_workspace_bytes(descs, count, true);
+  const size_t b = batch_workspace_bytes(descs, count, false);
+  return (a == 0 || b == 0) ? 0 : std::max(a, b);
+}
+
 // The batch tables of plan P (built for workspace ws) in host memory at h.
 void write_tables(const BatchPlan& P, char* h) {
   std::memcpy(h, P.fac.data(), P.fac.size() * sizeof(BatchFactor));
@@ -417,7 +435,8 @@ hipError_t run_planned(hipStream_t st, const BatchPlan& P, char* ws, int64_t cou
   const BatchFactor* d_fac = (const BatchFactor*)ws;
   if (P.queued)
     return run_sysblk_qbatch(st, d_fac, count, (const QItem*)(ws + P.off_items),
-                             (int64_t)P.items.size(), (int32_t*)(ws + P.off_ticket));
+                             (int64_t)P.items.size(), (int32_t*)(ws + P.off_ticket), P.grid,
+                             P.poll);
   return run_sysblk_batch(st, d_fac, count, (const BatchEntry*)(ws + P.off_ent), P.steps.data(),
                           (int64_t)P.steps.size());
 }
@@ -426,20 +445,86 @@ int64_t batch_steps_of(const cholmod_desc& d) {
   return (d.n <= 0 || d.k <= 0) ? 0 : ceil_div(d.n, kBlock) * ceil_div(d.k, kPass);
 }
 
+// ------------------------------------------------------------ launch plans
+// The plan that cholmod_update_batched uses for a batch comes from a table
+// indexed by the batch's dominant (storage type, n bucket, k bucket): the
+// bucket holding most of the batch's work, n^2 k summed over its factors.
+// The table starts with the default plan everywhere; cholmod_set_plan fills
+// it, normally from a plan cache that the autotuner wrote.
+constexpr int kNBuckets = 5, kKBuckets = 4;
+const int64_t kNBucketTop[kNBuckets - 1] = {256, 1024, 4096, 16384};
+const int64_t kKBucketTop[kKBuckets - 1] = {16, 32, 64};
+
+cholmod_plan default_plan() {
+  cholmod_plan p;
+  p.schedule = CHOLMOD_SCHED_QUEUED;
+  p.grid = 0;
+  p.order = CHOLMOD_ORDER_BLOCK;
+  p.poll = 2;
+  return p;
+}
+
+struct PlanTable {
+  cholmod_plan p[2][kNBuckets][kKBuckets];
+  PlanTable() {
+    for (auto& a : p)
+      for (auto& b : a)
+        for (auto& c : b) c = default_plan();
+  }
+};
+std::mutex g_plan_mu;
+PlanTable g_plans;
+
+int bucket_of(int64_t v, const int64_t* tops, int n) {
+  int b = 0;
+  while (b < n - 1 && v > tops[b]) ++b;
+  return b;
+}
+
+bool plan_ok(const cholmod_plan& p) {
+  return (p.schedule == CHOLMOD_SCHED_QUEUED || p.schedule == CHOLMOD_SCHED_STEPPED) &&
+         p.grid >= 0 && p.grid <= 65536 &&
+         (p.order == CHOLMOD_ORDER_BLOCK || p.order == CHOLMOD_ORDER_FACTOR) && p.poll >= 0 &&
+         p.poll <= 2;
+}
+
+// The table's plan for a batch (descriptors already validated).
+cholmod_plan select_plan(const cholmod_desc* descs, int64_t count) {
+  double work[2][kNBuckets][kKBuckets] = {};
+  for (int64_t f = 0; f < count; ++f) {
+    const cholmod_desc& d = descs[f];
+    const int t = d.dtype == CHOLMOD_F64 ? 0 : 1;
+    work[t][bucket_of(d.n, kNBucketTop, kNBuckets)][bucket_of(d.k, kKBucketTop, kKBuckets)] +=
+        (double)d.n * (double)d.n * (double)d.k;
+  }
+  int bt = 0, bn = 0, bk = 0;
+  for (int t = 0; t < 2; ++t)
+    for (int a = 0; a < kNBuckets; ++a)
+      for (int b = 0; b < kKBuckets; ++b)
+        if (work[t][a][b] > work[bt][bn][bk]) bt = t, bn = a, bk = b;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  return g_plans.p[bt][bn][bk];
+}
+
 int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_bytes,
                   int64_t* d_info, hipStream_t st, void* stage, size_t stage_bytes,
-                  const std::function<int(int64_t)>* after_step, int64_t* d_done) {
+                  const std::function<int(int64_t)>* after_step, int64_t* d_done,
+                  const cholmod_plan* plan) {
   BatchPlan P;
-  const bool queued = after_step == nullptr;
-  int rc = plan_batch(descs, count, nullptr, &P, queued);
+  const cholmod_plan lp = plan ? *plan : default_plan();
+  if (!plan_ok(lp)) return CHOLMOD_ERR_ARG;
+  const bool queued = after_step == nullptr && lp.schedule == CHOLMOD_SCHED_QUEUED;
+  int rc = plan_batch(descs, count, nullptr, &P, queued, lp.order);
   if (rc) return rc;
   if (count == 0) return CHOLMOD_OK;
   if (d_info == nullptr || ((uintptr_t)d_info & 7u) != 0) return CHOLMOD_ERR_ARG;
   if (ws == nullptr || ws_bytes < P.total || ((uintptr_t)ws % kAlign) != 0)
     return CHOLMOD_ERR_ARG;
   if (stage == nullptr || stage_bytes < P.table_bytes) return CHOLMOD_ERR_ARG;
-  rc = plan_batch(descs, count, (char*)ws, &P, queued);
+  rc = plan_batch(descs, count, (char*)ws, &P, queued, lp.order);
   if (rc) return rc;
+  P.grid = lp.grid;
+  P.poll = lp.poll;
   for (int64_t f = 0; f < count; ++f) {
     P.fac[f].info = d_info + f;
     if (queued && d_done) P.fac[f].done = d_done + f;
@@ -934,14 +1019,16 @@ int cholmod_batch_graph_create(const cholmod_desc* descs, int64_t count, void* w
   if (out == nullptr) return CHOLMOD_ERR_ARG;
   *out = nullptr;
   if (count < 1) return CHOLMOD_ERR_ARG;
-  const size_t tb = batch_table_bytes(descs, count);
-  const size_t need = batch_workspace_bytes(descs, count);
-  if (tb == 0 || need == 0) return CHOLMOD_ERR_ARG;
+  const size_t need = batch_workspace_bytes_any(descs, count);
+  if (need == 0) return CHOLMOD_ERR_ARG;
   if (d_info == nullptr || ((uintptr_t)d_info & 7u) != 0) return CHOLMOD_ERR_ARG;
   if (ws == nullptr || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return CHOLMOD_ERR_ARG;
+  const cholmod_plan lp = select_plan(descs, count);
   BatchPlan P;
-  int rc = plan_batch(descs, count, (char*)ws, &P);
+  int rc = plan_batch(descs, count, (char*)ws, &P, lp.schedule == CHOLMOD_SCHED_QUEUED, lp.order);
   if (rc) return rc;
+  P.grid = lp.grid;
+  P.poll = lp.poll;
   for (int64_t f = 0; f < count; ++f) P.fac[f].info = d_info + f;
   std::vector<char> tables(P.table_bytes);
   write_tables(P, tables.data());
@@ -983,19 +1070,60 @@ int cholmod_batch_graph_destroy(cholmod_batch_graph* g) {
 }
 
 size_t cholmod_workspace_bytes_batched(const cholmod_desc* descs, int64_t count) {
-  return batch_workspace_bytes(descs, count);
+  return batch_workspace_bytes_any(descs, count);
+}
+
+int cholmod_plan_bucket(int64_t n, int64_t k, int* n_bucket, int* k_bucket) {
+  if (n < 0 || k < 0) return CHOLMOD_ERR_ARG;
+  if (n_bucket) *n_bucket = bucket_of(n, kNBucketTop, kNBuckets);
+  if (k_bucket) *k_bucket = bucket_of(k, kKBucketTop, kKBuckets);
+  return CHOLMOD_OK;
+}
+
+int cholmod_set_plan(int dtype, int n_bucket, int k_bucket, const cholmod_plan* plan) {
+  if (dtype != CHOLMOD_F64 && dtype != CHOLMOD_F32S) return CHOLMOD_ERR_ARG;
+  if (n_bucket < 0 || n_bucket >= kNBuckets || k_bucket < 0 || k_bucket >= kKBuckets)
+    return CHOLMOD_ERR_ARG;
+  if (plan == nullptr || !plan_ok(*plan)) return CHOLMOD_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plans.p[dtype == CHOLMOD_F64 ? 0 : 1][n_bucket][k_bucket] = *plan;
+  return CHOLMOD_OK;
+}
+
+int cholmod_get_plan(int dtype, int n_bucket, int k_bucket, cholmod_plan* plan) {
+  if (dtype != CHOLMOD_F64 && dtype != CHOLMOD_F32S) return CHOLMOD_ERR_ARG;
+  if (n_bucket < 0 || n_bucket >= kNBuckets || k_bucket < 0 || k_bucket >= kKBuckets)
+    return CHOLMOD_ERR_ARG;
+  if (plan == nullptr) return CHOLMOD_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  *plan = g_plans.p[dtype == CHOLMOD_F64 ? 0 : 1][n_bucket][k_bucket];
+  return CHOLMOD_OK;
+}
+
+int cholmod_compute_units(void) {
+  int n = 0;
+  if (hipGetDevice(&n) != hipSuccess) return 0;
+  return compute_units();
 }
 
 int cholmod_update_batched(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_bytes,
                            int64_t* d_info, cholmod_stream_t stream) {
+  return cholmod_update_batched_plan(descs, count, nullptr, ws, ws_bytes, d_info, stream);
+}
+
+int cholmod_update_batched_plan(const cholmod_desc* descs, int64_t count,
+                                const cholmod_plan* plan, void* ws, size_t ws_bytes,
+                                int64_t* d_info, cholmod_stream_t stream) {
   // every argument check happens here, before any HIP call
   if (count < 0) return CHOLMOD_ERR_ARG;
   if (count == 0) return CHOLMOD_OK;
-  const size_t tb = batch_table_bytes(descs, count);
-  const size_t need = batch_workspace_bytes(descs, count);
-  if (tb == 0 || need == 0) return CHOLMOD_ERR_ARG;
+  if (plan != nullptr && !plan_ok(*plan)) return CHOLMOD_ERR_ARG;
+  const size_t need = batch_workspace_bytes_any(descs, count);
+  if (need == 0) return CHOLMOD_ERR_ARG;
   if (d_info == nullptr || ((uintptr_t)d_info & 7u) != 0) return CHOLMOD_ERR_ARG;
   if (ws == nullptr || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return CHOLMOD_ERR_ARG;
+  const cholmod_plan lp = plan ? *plan : select_plan(descs, count);
+  const size_t tb = batch_table_bytes(descs, count, lp.schedule == CHOLMOD_SCHED_QUEUED);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return CHOLMOD_ERR_HIP;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -1016,7 +1144,8 @@ int cholmod_update_batched(const cholmod_desc* descs, int64_t count, void* ws, s
     d.stage_bytes = tb;
   }
   hipStream_t st = (hipStream_t)stream;
-  const int rc = enqueue_batch(descs, count, ws, ws_bytes, d_info, st, d.stage, d.stage_bytes);
+  const int rc = enqueue_batch(descs, count, ws, ws_bytes, d_info, st, d.stage, d.stage_bytes,
+                               nullptr, nullptr, &lp);
   if (rc) return rc;
   if (hipEventRecord(d.stage_done, st) != hipSuccess) return CHOLMOD_ERR_HIP;
   d.stage_pending = true;

@@ -294,9 +294,14 @@ struct cholmod_server {
       else s.stage_bytes = tb;
     }
     for (int64_t i = 0; i < count; ++i) s.h_done[i] = kDoneEmpty;
-    if (rc == CHOLMOD_OK)
+    if (rc == CHOLMOD_OK) {
+      // the tuned launch shape of such a batch, always the queued schedule
+      // (its factors report completion one by one)
+      cholmod_plan lp = chm::select_plan(descs.data(), count);
+      lp.schedule = CHOLMOD_SCHED_QUEUED;
       rc = chm::enqueue_batch(descs.data(), count, ws, plan, d_info, s.stream, s.stage,
-                              s.stage_bytes, nullptr, s.d_done);
+                              s.stage_bytes, nullptr, s.d_done, &lp);
+    }
     if (rc == CHOLMOD_OK &&
         hipMemcpyAsync(s.h_info, d_info, count * sizeof(int64_t), hipMemcpyDeviceToHost,
                        s.stream) != hipSuccess)

@@ -300,27 +300,29 @@ __device__ __forceinline__ void w2x2_load(ST (&w)[kOwnCols], const ST* __restric
     }
 }
 
-// One sub-step s of an apply lane: records qc (row s - h), the row that
-// enters the lanes of h = 0 at the next sub-step in fc; loads the next
-// records into qn and the row after into fn.  The tile is in LDS at `tile`
-// with row stride LD.  Callers alternate two register sets, so that nothing
-// is copied between sub-steps.
-template <int SG, typename ST, int LD>
-__device__ __forceinline__ void sub2x2(const ST* tile_in, ST* tile, const RotRec* rp,
-                                       int s, int h, int c0, int hf, bool first,
-                                       ST (&w)[kOwnCols], ST (&xin)[2], const RotRec (&qc)[2],
-                                       RotRec (&qn)[2], const ST (&fc)[2], ST (&fn)[2]) {
-  const int r = s - h;
+// One sub-step s of an apply lane: records qc (row s - h); loads the next
+// records into qn.  The tile is in LDS at `tile` with row stride LD.  Row
+// s + 1 of the tile, which the lanes of h = 0 take at the next sub-step, is
+// read at the start and becomes the fill value of the shift at the end, so
+// its load latency is hidden and no register is copied for it (every lane
+// reads it: one LDS broadcast per column pair costs less than masking the
+// others off).  WRITE: the sub-step may finish a row (s >= hf; before, the
+// lanes of h = hf still hold rows < 0), which lane h = hf stores.  DRAIN
+// (s >= 63): the lanes of h = 0 enter rows past the tile, whose records are
+// identity; they take 0, which such a rotation passes through exactly (a
+// value read past the tile could be a NaN, and 0 * NaN would spoil V).
+// Callers alternate two record sets, so that nothing is copied between
+// sub-steps.
+template <int SG, typename ST, int LD, bool WRITE, bool DRAIN>
+__device__ __forceinline__ void sub2x2(ST* tile, const RotRec* rp, int s, int h, int c0,
+                                       int hf, bool first, ST (&w)[kOwnCols], ST (&xin)[2],
+                                       const RotRec (&qc)[2], RotRec (&qn)[2]) {
+  ST fill[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) fill[u] = DRAIN ? (ST)0 : tile[(s + 1) * LD + c0 + u];
   // s + 1 <= 71: record rows up to 87
   qn[0] = rp[(s + 1) * kKP];
   qn[1] = rp[(s + 1) * kKP + 1];
-  {
-    // only lanes h = 0 use it; the others read the same address (one LDS
-    // broadcast per column pair), which costs less than masking them off
-    const int rn2 = imin(s + 2, kBR - 1);
-#pragma unroll
-    for (int u = 0; u < 2; ++u) fn[u] = (ST)tile_in[rn2 * LD + c0 + u];
-  }
   const ST ca = (ST)qc[0].c, sa = (ST)qc[0].s, ia = (ST)qc[0].ic;
   const ST cb = (ST)qc[1].c, sb = (ST)qc[1].s, ib = (ST)qc[1].ic;
   ST x1[2], x2[2];
@@ -331,12 +333,43 @@ __device__ __forceinline__ void sub2x2(const ST* tile_in, ST* tile, const RotRec
     x2[u] = fma_t((ST)SG * sb, w[2 + u], x1[u]) * ib;
     w[2 + u] = fma_t(-sb, x2[u], cb * w[2 + u]);
   }
-  if (h == hf && r >= 0 && r < kBR) {
+  if (WRITE && h == hf) {
+    const int r = s - hf;  // in [0, 64): s < 64 + hf
 #pragma unroll
     for (int u = 0; u < 2; ++u) tile[r * LD + c0 + u] = first ? x1[u] : x2[u];
   }
 #pragma unroll
-  for (int u = 0; u < 2; ++u) xin[u] = sb_shr<2>(x2[u], fc[u]);
+  for (int u = 0; u < 2; ++u) xin[u] = sb_shr<2>(x2[u], fill[u]);
+}
+
+// Sub-steps [s, lim) of an apply lane (s is advanced); qa holds the records
+// of sub-step s and, on return, those of sub-step lim.
+template <int SG, typename ST, int LD>
+__device__ __forceinline__ void sub2x2_run(ST* tile, const RotRec* rp, int& s, int lim, int h,
+                                           int c0, int hf, bool first, ST (&w)[kOwnCols],
+                                           ST (&xin)[2], RotRec (&qa)[2]) {
+  RotRec qb[2];
+  for (; s < lim && s < hf; ++s) {  // no row is finished yet
+    sub2x2<SG, ST, LD, false, false>(tile, rp, s, h, c0, hf, first, w, xin, qa, qb);
+    qa[0] = qb[0];
+    qa[1] = qb[1];
+  }
+  const int lmain = imin(lim, kBR - 1);  // sub-steps whose next row is in the tile
+  for (; s + 2 <= lmain; s += 2) {
+    sub2x2<SG, ST, LD, true, false>(tile, rp, s, h, c0, hf, first, w, xin, qa, qb);
+    sub2x2<SG, ST, LD, true, false>(tile, rp, s + 1, h, c0, hf, first, w, xin, qb, qa);
+  }
+  if (s < lmain) {
+    sub2x2<SG, ST, LD, true, false>(tile, rp, s, h, c0, hf, first, w, xin, qa, qb);
+    ++s;
+    qa[0] = qb[0];
+    qa[1] = qb[1];
+  }
+  for (; s < lim; ++s) {  // the drain: at most hf + 1 sub-steps
+    sub2x2<SG, ST, LD, true, true>(tile, rp, s, h, c0, hf, first, w, xin, qa, qb);
+    qa[0] = qb[0];
+    qa[1] = qb[1];
+  }
 }
 
 // Apply the records staged in sh.R (the block's 64 rows, identity records
@@ -351,20 +384,13 @@ __device__ __forceinline__ void apply2x2(SbLds& sh, ST* tile, int kc_, int lt,
   const int hf = (kc - 1) >> 1;      // lane holding rotation kc - 1
   const bool first = (kc & 1) != 0;  // ... as the first of its pair
   const int S = kBR + hf;            // row 63 reaches lane hf at sub-step 63 + hf
-  ST xin[2], fa[2], fb[2] = {(ST)0, (ST)0};
+  ST xin[2];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    xin[u] = (ST)tile[c0 + u];
-    fa[u] = (ST)tile[LD + c0 + u];
-  }
+  for (int u = 0; u < 2; ++u) xin[u] = (ST)tile[c0 + u];
   const RotRec* rp = &sh.R[kPad - h][2 * h];
-  RotRec qa[2] = {rp[0], rp[1]}, qb[2];
+  RotRec qa[2] = {rp[0], rp[1]};
   int s = 0;
-  for (; s + 2 <= S; s += 2) {
-    sub2x2<SG, ST, LD>(tile, tile, rp, s, h, c0, hf, first, w, xin, qa, qb, fa, fb);
-    sub2x2<SG, ST, LD>(tile, tile, rp, s + 1, h, c0, hf, first, w, xin, qb, qa, fb, fa);
-  }
-  if (s < S) sub2x2<SG, ST, LD>(tile, tile, rp, s, h, c0, hf, first, w, xin, qa, qb, fa, fb);
+  sub2x2_run<SG, ST, LD>(tile, rp, s, S, h, c0, hf, first, w, xin, qa);
 }
 
 // ------------------------------------------------------------------ chain
@@ -943,7 +969,7 @@ template <int SG, typename ST, int KCF>
 __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
                                             ST (&w)[kOwnCols],
                                             const GRec<ST>* __restrict__ T, int64_t deadline,
-                                            bool next) {
+                                            bool next, int poll) {
   using U = typename RecBits<ST>::U;
   constexpr U kE = RecBits<ST>::kEmpty;
   const int kc = KCF ? KCF : kc_;
@@ -968,12 +994,9 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
     const int S = kBR + hf;                // row 63 reaches lane hf at sub-step 63 + hf
     ST* const tile = tile_a<ST>(sh);
     constexpr int LD = kLdA;
-    ST xin[2], fa[2], fb[2] = {(ST)0, (ST)0};  // fa, fb: only lanes h = 0 use them
+    ST xin[2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      xin[u] = (ST)tile[c0 + u];
-      fa[u] = (ST)tile[LD + c0 + u];
-    }
+    for (int u = 0; u < 2; ++u) xin[u] = (ST)tile[c0 + u];
     // records of (row s - h, rotations 2h and 2h+1) at rp[s * kKP], rp[s * kKP + 1]
     const RotRec* rp = &sh.R[kPad - h][2 * h];
     int s = 0;
@@ -981,17 +1004,8 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
       __syncthreads();
       const int up = staged_prefix(rd & 1);
       const int lim = up >= kBR ? S : up;  // rows <= s - h < up are staged
-      RotRec qa[2] = {rp[s * kKP], rp[s * kKP + 1]}, qb[2];
-      for (; s + 2 <= lim; s += 2) {
-        sub2x2<SG, ST, LD>(tile, tile, rp, s, h, c0, hf, first, w, xin, qa, qb, fa, fb);
-        sub2x2<SG, ST, LD>(tile, tile, rp, s + 1, h, c0, hf, first, w, xin, qb, qa, fb, fa);
-      }
-      if (s < lim) {
-        sub2x2<SG, ST, LD>(tile, tile, rp, s, h, c0, hf, first, w, xin, qa, qb, fa, fb);
-        ++s;
-        fa[0] = fb[0];
-        fa[1] = fb[1];
-      }
+      RotRec qa[2] = {rp[s * kKP], rp[s * kKP + 1]};
+      sub2x2_run<SG, ST, LD>(tile, rp, s, lim, h, c0, hf, first, w, xin, qa);
       if (up >= kBR) break;
     }
   } else {
@@ -1040,7 +1054,8 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
             nr = 16;
             break;
           }
-          if (next) __builtin_amdgcn_s_sleep(1);
+          if (next || poll == 0) __builtin_amdgcn_s_sleep(1);
+          else if (poll == 1) __builtin_amdgcn_s_sleep(20);
           else __builtin_amdgcn_s_sleep(100);
           fetch(upw);
           nr = __builtin_ctz(~ready_rows());
@@ -1088,7 +1103,7 @@ struct OwnF {
 // triangle goes to L, else back to sh.Lb for the next pass.
 template <int SG, typename ST, int KCF>
 __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, int bbc,
-                                           int pass, bool last, int64_t deadline) {
+                                           int pass, bool last, int64_t deadline, int poll) {
   const int tid = threadIdx.x;
   const int64_t m0 = (int64_t)pass * kKP;
   const int kc = KCF ? KCF : (int)(F.k - m0 < kKP ? F.k - m0 : kKP);
@@ -1119,7 +1134,7 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
     if (b + 1 < j) tile_issue_a(tr, F.L, F.ldl, (int64_t)(b + 1) * kBR, pj, bbc);
     const int64_t pb = (int64_t)b * kBR;
     __syncthreads();
-    owner_apply<SG, ST, KCF>(sh, kc, pb, w, T, deadline, b == j - 1);
+    owner_apply<SG, ST, KCF>(sh, kc, pb, w, T, deadline, b == j - 1, poll);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kTilePerThread; ++q) {
@@ -1152,7 +1167,7 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
 // it: the chains of all passes together take about (blocks + passes - 1)
 // block chains.
 template <int SG, typename ST, bool SPEC16>
-__device__ __forceinline__ void owner_item(SbLds& sh, const OwnF<ST>& F, int j) {
+__device__ __forceinline__ void owner_item(SbLds& sh, const OwnF<ST>& F, int j, int poll) {
   const int tid = threadIdx.x;
   const int64_t deadline = wall_clock64() + kWaitTicks;
   const int64_t pj = (int64_t)j * kBR;
@@ -1167,9 +1182,9 @@ __device__ __forceinline__ void owner_item(SbLds& sh, const OwnF<ST>& F, int j) 
   for (int p = 0; p < passes; ++p) {
     const bool last = p + 1 == passes;
     if (SPEC16 && F.k - (int64_t)p * kKP >= kKP)
-      owner_pass<SG, ST, kKP>(sh, F, j, bbc, p, last, deadline);
+      owner_pass<SG, ST, kKP>(sh, F, j, bbc, p, last, deadline, poll);
     else
-      owner_pass<SG, ST, 0>(sh, F, j, bbc, p, last, deadline);
+      owner_pass<SG, ST, 0>(sh, F, j, bbc, p, last, deadline, poll);
   }
 }
 
@@ -1188,12 +1203,12 @@ __global__ __launch_bounds__(kThreads) void k_sb_queue(OwnF<ST> F, int nitems,
     const int j = sh.tk;
     __syncthreads();
     if (j >= nitems) break;
-    owner_item<SG, ST, true>(sh, F, j);
+    owner_item<SG, ST, true>(sh, F, j, 2);
   }
 }
 
 // The owner item (block j, every pass) of one factor of a queued batch.
-__device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int j) {
+__device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int j, int poll) {
   if (B.dtype == kStoreF64) {
     OwnF<double> F;
     F.L = (double*)B.L;
@@ -1204,8 +1219,8 @@ __device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int
     F.n = B.n;
     F.k = B.k;
     F.ldl = B.ldl;
-    if (B.sigma > 0) owner_item<1, double, true>(sh, F, j);
-    else owner_item<-1, double, true>(sh, F, j);
+    if (B.sigma > 0) owner_item<1, double, true>(sh, F, j, poll);
+    else owner_item<-1, double, true>(sh, F, j, poll);
   } else {
     OwnF<float> F;
     F.L = (float*)B.L;
@@ -1216,8 +1231,8 @@ __device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int
     F.n = B.n;
     F.k = B.k;
     F.ldl = B.ldl;
-    if (B.sigma > 0) owner_item<1, float, true>(sh, F, j);
-    else owner_item<-1, float, true>(sh, F, j);
+    if (B.sigma > 0) owner_item<1, float, true>(sh, F, j, poll);
+    else owner_item<-1, float, true>(sh, F, j, poll);
   }
 }
 
@@ -1232,7 +1247,7 @@ __device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int
 __global__ __launch_bounds__(kThreads) void k_sb_qbatch(const BatchFactor* __restrict__ fac,
                                                         const QItem* __restrict__ items,
                                                         int nitems,
-                                                        int32_t* __restrict__ ticket) {
+                                                        int32_t* __restrict__ ticket, int poll) {
   __shared__ SbLds sh;
   for (;;) {
     if (threadIdx.x == 0)
@@ -1243,7 +1258,7 @@ __global__ __launch_bounds__(kThreads) void k_sb_qbatch(const BatchFactor* __res
     if (t >= nitems) break;
     const QItem it = items[t];
     const BatchFactor B = fac[it.f];
-    qbatch_item(sh, B, it.j);  // ends with a barrier: every wave's stores are issued
+    qbatch_item(sh, B, it.j, poll);  // ends with a barrier: every wave's stores are issued
     if (threadIdx.x == 0 && B.done != nullptr) {
       __threadfence();  // the workgroup's stores, device-wide
       if (__hip_atomic_fetch_add(B.left, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1) {
@@ -1512,20 +1527,25 @@ hipError_t run_sysblk_batch_step(hipStream_t st, const BatchFactor* d_fac,
   return hipGetLastError();
 }
 
-// A queued batch: the preparation launch and one persistent owner launch.
+// A queued batch: the preparation launch and one persistent owner launch of
+// `grid` workgroups (0: one per compute unit; never more than the items);
+// poll: how long owners far from the chain sleep between polls (0..2).
 hipError_t run_sysblk_qbatch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
-                             const QItem* d_items, int64_t nitems, int32_t* d_ticket) {
+                             const QItem* d_items, int64_t nitems, int32_t* d_ticket, int grid,
+                             int poll) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_prepare_qbatch, dim3(8, (unsigned)count), dim3(256), 0, st, d_fac,
                      d_ticket);
   if (nitems > 0) {
-    const int lim = owner_grid_limit();
-    const unsigned grid = (unsigned)(nitems < lim ? nitems : lim);
-    hipLaunchKernelGGL(k_sb_qbatch, dim3(grid), dim3(kThreads), 0, st, d_fac, d_items,
-                       (int)nitems, d_ticket);
+    int64_t g = grid > 0 ? grid : owner_grid_limit();
+    if (g > nitems) g = nitems;
+    hipLaunchKernelGGL(k_sb_qbatch, dim3((unsigned)g), dim3(kThreads), 0, st, d_fac, d_items,
+                       (int)nitems, d_ticket, poll);
   }
   return hipGetLastError();
 }
+
+int compute_units() { return owner_grid_limit(); }
 
 hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
                             const BatchEntry* d_ent, const BatchStep* steps, int64_t nsteps) {

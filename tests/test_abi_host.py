@@ -237,3 +237,49 @@ def test_noalloc_rejects_oversized_problems_on_host(nat):
     assert lib.cholmod_update_noalloc(fake, fake, 10, 2, 5, 1, fake, None) == nat.ERR_ARG
     assert lib.cholmod_update_noalloc(fake, fake, 10, 2, 10, 0, fake, None) == nat.ERR_ARG
     assert lib.cholmod_update_noalloc(fake, fake, 10, 2, 10, 1, None, None) == nat.ERR_ARG
+
+
+def test_plan_table_on_host(nat):
+    """Plan table and bucket functions: pure host code."""
+    lib = nat.load()
+    nb, kb = ctypes.c_int(-1), ctypes.c_int(-1)
+    for (n, k, en, ek) in [(64, 1, 0, 0), (256, 16, 0, 0), (257, 17, 1, 1), (4096, 32, 2, 1),
+                           (4097, 33, 3, 2), (16385, 65, 4, 3)]:
+        assert lib.cholmod_plan_bucket(n, k, ctypes.byref(nb), ctypes.byref(kb)) == nat.OK
+        assert (nb.value, kb.value) == (en, ek), (n, k)
+    assert lib.cholmod_plan_bucket(-1, 1, None, None) == nat.ERR_ARG
+    p = nat.Plan()
+    assert lib.cholmod_get_plan(nat.F64, 2, 1, ctypes.byref(p)) == nat.OK
+    keep = nat.Plan(p.schedule, p.grid, p.order, p.poll)
+    q = nat.Plan(nat.SCHED_QUEUED, 128, nat.ORDER_FACTOR, 0)
+    assert lib.cholmod_set_plan(nat.F64, 2, 1, ctypes.byref(q)) == nat.OK
+    r = nat.Plan()
+    assert lib.cholmod_get_plan(nat.F64, 2, 1, ctypes.byref(r)) == nat.OK
+    assert (r.schedule, r.grid, r.order, r.poll) == (0, 128, 1, 0)
+    assert lib.cholmod_set_plan(nat.F64, 2, 1, ctypes.byref(keep)) == nat.OK
+    for bad in [nat.Plan(2, 0, 0, 2), nat.Plan(0, -1, 0, 2), nat.Plan(0, 0, 2, 2),
+                nat.Plan(0, 0, 0, 3)]:
+        assert lib.cholmod_set_plan(nat.F64, 0, 0, ctypes.byref(bad)) == nat.ERR_ARG
+    assert lib.cholmod_set_plan(7, 0, 0, ctypes.byref(q)) == nat.ERR_ARG
+    assert lib.cholmod_set_plan(nat.F64, 5, 0, ctypes.byref(q)) == nat.ERR_ARG
+    assert lib.cholmod_set_plan(nat.F64, 0, 4, ctypes.byref(q)) == nat.ERR_ARG
+    assert lib.cholmod_get_plan(nat.F64, 0, 0, None) == nat.ERR_ARG
+
+
+def test_plan_cache_file_loads(nat, tmp_path):
+    """A plan cache in the tuner's format goes into the library's table."""
+    import json
+    from paper_1011_1173_amd import tune
+    lib = nat.load()
+    path = tmp_path / "plans.json"
+    json.dump({"arch": "gfx950", "entries": [
+        {"dtype": 1, "n_bucket": 3, "k_bucket": 2,
+         "plan": {"schedule": 1, "grid": 0, "order": 0, "poll": 1}}]}, open(path, "w"))
+    old = nat.Plan()
+    assert lib.cholmod_get_plan(nat.F32S, 3, 2, ctypes.byref(old)) == nat.OK
+    assert tune.load_plans(str(path)) == 1
+    r = nat.Plan()
+    assert lib.cholmod_get_plan(nat.F32S, 3, 2, ctypes.byref(r)) == nat.OK
+    assert (r.schedule, r.poll) == (1, 1)
+    assert lib.cholmod_set_plan(nat.F32S, 3, 2, ctypes.byref(old)) == nat.OK
+    assert tune.load_plans(str(tmp_path / "missing.json")) == 0

@@ -101,3 +101,24 @@ def test_batched_uneven_pool(orc):
     for i in range(count):
         assert stat1[i][0] == 0 and stats[i][0] == 0, i
         assert np.array_equal(single[i], batched[i]), i
+
+
+def test_every_tuned_plan_equals_single_bitwise(orc):
+    """Every launch plan the autotuner may pick (stepped or queued; queued
+    with fewer workgroups, factor-major order, other poll levels) leaves each
+    factor of the mixed batch bit for bit where the single-factor path does."""
+    import paper_1011_1173_amd as chm
+    from paper_1011_1173_amd import _native, tune
+    cus = int(_native.load().cholmod_compute_units())
+    assert cus > 0
+    cases = [make_case(orc, n, k, sg, f32, 5100 + i) + (sg, f32)
+             for i, (n, k, sg, f32) in enumerate(MIXED)]
+    single, stat1, _, _ = run_both(cases)
+    for plan in tune.candidates(cus) + [{"schedule": 0, "grid": 1, "order": 1, "poll": 1}]:
+        print_case("batched-plan", **plan)
+        Ls = [to_dev(L, f32) for L, _, _, f32 in cases]
+        Vs = [to_dev(V, f32) for _, V, _, f32 in cases]
+        stats = chm.update_batched(Ls, Vs, [c[2] for c in cases], plan=plan)
+        for i, L in enumerate(Ls):
+            assert stats[i][0] == 0, (plan, i, stats[i])
+            assert np.array_equal(single[i], L.cpu().numpy().astype(np.float64)), (plan, i)
