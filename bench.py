@@ -94,6 +94,8 @@ def parse():
                     help="served workload: arrival window per load level")
     ap.add_argument("--served-factors", type=int, default=64)
     ap.add_argument("--served-max-n", type=int, default=16384)
+    ap.add_argument("--rotations", action="store_true",
+                    help="apply every block by its rotations (no block maps), for comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy before the timed region, as the "
                          "reference dispatch for hardware byte counters")
@@ -177,6 +179,8 @@ def batched(args):
     import torch
     import paper_1011_1173_amd as chm
     from paper_1011_1173_amd import inputs
+    plan = ({"schedule": 0, "grid": 0, "order": 0, "poll": 2, "maps": 0} if args.rotations
+            else None)
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -226,7 +230,7 @@ def batched(args):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            pb = chm.update_batched_async(Ls, Vs, sg, stream=stream)
+            pb = chm.update_batched_async(Ls, Vs, sg, stream=stream, plan=plan)
             e1.record(stream)
         st = pb.statuses()
         assert all(x[0] == 0 for x in st), st
@@ -251,7 +255,8 @@ def batched(args):
                     if use_graph:
                         g.launch(stream)
                     else:
-                        pb = chm.update_batched_async(Ls, Vfix, [sgn] * nf, stream=stream)
+                        pb = chm.update_batched_async(Ls, Vfix, [sgn] * nf, stream=stream,
+                                                      plan=plan)
                     e1.record(stream)
                     stat = g.statuses() if use_graph else pb.statuses()
                     assert all(x[0] == 0 for x in stat), stat
@@ -265,7 +270,8 @@ def batched(args):
            "value": nf / (med * 1e-3), "unit": "modifications/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": med,
            "higher_is_better": True, "dtype": args.batch_dtype, "data": "synthetic",
-           "config": {"workload": "batched: 256 factors, n ~ U{64..4096}, k ~ U{1..32}, "
+           "config": {"block_apply": "rotations" if args.rotations else "maps for far blocks",
+                      "workload": "batched: 256 factors, n ~ U{64..4096}, k ~ U{1..32}, "
                                   "update or downdate 50/50 per factor",
                       "dense_GB": sum(es * n * n for n in ns) / 1e9},
            "batch_ms": {"median": med, "min": ts[0], "max": ts[-1]},
@@ -305,7 +311,8 @@ def sweep(args):
                             e0 = torch.cuda.Event(enable_timing=True)
                             e1 = torch.cuda.Event(enable_timing=True)
                             e0.record(stream)
-                            pend = chm.update_async(L, V, sg, stream=stream)
+                            pend = chm.update_async(L, V, sg, stream=stream,
+                                                    rotations=args.rotations)
                             e1.record(stream)
                             st, _, _ = pend.status()
                             assert st == 0, (n, k, dt, st)
@@ -328,7 +335,8 @@ def sweep(args):
     out = {"metric": "single-factor sweep (ms per modification, effective GB/s)",
            "value": None, "unit": "see rows", "n_gpus": 1, "higher_is_better": False,
            "dtype": "f64+f32s", "data": "synthetic",
-           "config": {"workload": "sweep: n in {1e4, 2e4, 4e4} x k in {1, 16, 64} x "
+           "config": {"block_apply": "rotations" if args.rotations else "maps for far blocks",
+                      "workload": "sweep: n in {1e4, 2e4, 4e4} x k in {1, 16, 64} x "
                                   "{FP64, FP32 storage}, update then matching downdate"},
            "rows": rows}
     print(json.dumps(out))
@@ -566,13 +574,14 @@ def main():
     L = inputs.spd_factor(n, seed=2, device="cuda")
     V = inputs.update_vectors(n, k, seed=2, device="cuda")
     L0 = L.clone()
+    rot = args.rotations
     stream = torch.cuda.current_stream(dev)
     ws = torch.empty(chm.workspace_bytes(n, k), dtype=torch.uint8, device=dev)
     info = torch.empty(2, dtype=torch.int64, device=dev)
 
     def step():
-        chm.update_async(L, V, +1, stream=stream, workspace=ws, info=info[0:1])
-        chm.update_async(L, V, -1, stream=stream, workspace=ws, info=info[1:2])
+        chm.update_async(L, V, +1, stream=stream, workspace=ws, info=info[0:1], rotations=rot)
+        chm.update_async(L, V, -1, stream=stream, workspace=ws, info=info[1:2], rotations=rot)
 
     if args.calibrate_copy:
         # one elementwise kernel that reads 256 MiB and writes 256 MiB
@@ -593,9 +602,9 @@ def main():
     t0 = time.perf_counter()
     ev[0].record(stream)
     for s in range(K):
-        chm.update_async(L, V, +1, stream=stream, workspace=ws, info=info[0:1])
+        chm.update_async(L, V, +1, stream=stream, workspace=ws, info=info[0:1], rotations=rot)
         ev[2 * s + 1].record(stream)
-        chm.update_async(L, V, -1, stream=stream, workspace=ws, info=info[1:2])
+        chm.update_async(L, V, -1, stream=stream, workspace=ws, info=info[1:2], rotations=rot)
         ev[2 * s + 2].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -617,7 +626,8 @@ def main():
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            chm.update_async(L, V, sg, stream=stream, workspace=ws, info=info[slot:slot + 1])
+            chm.update_async(L, V, sg, stream=stream, workspace=ws, info=info[slot:slot + 1],
+                             rotations=rot)
             e1.record(stream)
             e1.synchronize()
             cold.append(e0.elapsed_time(e1))
@@ -649,6 +659,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "rank-%d update then matching downdate, n=%d, FP64, ldl=n" % (k, n),
+                   "block_apply": "rotations" if rot else "maps for far blocks",
                    "n": n, "k": k, "modifications_per_step": 2},
         "effective_GBps": alg_bytes / (mean * 1e-3) / 1e9,
         "per_update_ms": {"median": med, "mean": mean, "min": per_sorted[0],

@@ -42,13 +42,21 @@
  *     rounded sqrt and division, no fused multiply-add).  Slow; intended to
  *     reproduce a serial reference bit for bit.
  *   default (fast): the same rotations, evaluated with reciprocal square
- *     roots refined by Newton steps, multiplication by 1/c instead of
+ *     roots refined by a third-order step, multiplication by 1/c instead of
  *     division, and fused multiply-adds; results agree with the exact
- *     evaluation to a relative residual far below 1e-12.  The fast mode's
- *     single launch per 16 columns of V has workgroups wait for records
- *     that earlier workgroups publish; such a wait is bounded, and a launch
- *     whose wait ran out (not expected while the GPU runs the launch)
- *     reports CHOLMOD_ERR_HIP.
+ *     evaluation to a relative residual far below 1e-12.  The fast mode runs
+ *     one persistent launch per modification (all 16-column passes of V);
+ *     its workgroups wait for rotation records and block maps that earlier
+ *     workgroups publish; such a wait is bounded, and a launch whose wait ran
+ *     out (not expected while the GPU runs the launch) reports
+ *     CHOLMOD_ERR_HIP.  A workgroup applies a block three or more blocks
+ *     before its own by the block's map -- the block's rotations multiplied
+ *     out into one 80 x 80 matrix, applied on the FP64 matrix cores -- which
+ *     equals the rotation-by-rotation Apply up to rounding (maps whose
+ *     entries exceed 2 in magnitude, as in a downdate close to
+ *     indefiniteness, are not used).
+ *   CHOLMOD_FLAG_ROTATIONS: the fast mode with every block applied by its
+ *     rotations, which is bit for bit the per-row fast schedule's result.
  */
 #ifndef CHOLMOD_MI355X_H
 #define CHOLMOD_MI355X_H
@@ -70,6 +78,7 @@ extern "C" {
 /* Flags for the _ex entry points. */
 #define CHOLMOD_FLAG_EXACT 1u     /* IEEE evaluation exactly as Algorithm 1 */
 #define CHOLMOD_FLAG_BLOCKED 2u   /* force the host-driven per-block schedule */
+#define CHOLMOD_FLAG_ROTATIONS 4u /* fast mode: every block by its rotations, no block maps */
 
 /* Storage types for workspace sizing. */
 #define CHOLMOD_F64 0
@@ -99,8 +108,9 @@ int cholmod_decode_info(int64_t info, int64_t k, int64_t *row, int64_t *col);
 /*
  * Bytes of device workspace needed by the _async/_ex entry points for an
  * n x k problem with the given storage type (CHOLMOD_F64 or CHOLMOD_F32S).
- * Returns 0 for invalid sizes.  The workspace holds the private copy of V
- * and the per-row rotation coefficients; it needs 256-byte alignment.
+ * Returns 0 for invalid sizes.  The workspace holds the private copy of V,
+ * the per-row rotation coefficients and the block maps (38,912 bytes per
+ * 64-row block and 16-column pass); it needs 256-byte alignment.
  */
 size_t cholmod_workspace_bytes(int64_t n, int64_t k, int dtype);
 
@@ -164,7 +174,8 @@ int cholmod_update_noalloc(double *L, const double *V, int64_t n, int64_t k, int
  * Compute (w, c, s, 1/c) and the Apply inside the block -- are evaluated in
  * binary64 from the stored values and rounded to binary32 when stored; the
  * Apply of a block's rotations to the columns right of the block runs in
- * binary32 with the coefficients rounded to binary32.  Accuracy: the
+ * binary32 with the coefficients rounded to binary32, or, by the block's
+ * map, in binary64 rounded to binary32 when stored.  Accuracy: the
  * relative Frobenius distance to the binary64 factor of the same (binary32)
  * inputs is about 1e-6 (bound tested: 1e-5).  Halves the memory traffic;
  * the serial chain is unchanged.  Layout, ownership and error reporting are
@@ -179,15 +190,21 @@ int cholmod_update_f32s(float *L, const float *V, int64_t n, int64_t k, int64_t 
 int cholmod_update_f32s_async(float *L, const float *V, int64_t n, int64_t k, int64_t ldl,
                               int sigma, void *ws, size_t ws_bytes, int64_t *d_info,
                               cholmod_stream_t stream);
+/* As cholmod_update_f32s_async with flags: 0 or CHOLMOD_FLAG_ROTATIONS. */
+int cholmod_update_f32s_ex(float *L, const float *V, int64_t n, int64_t k, int64_t ldl,
+                           int sigma, unsigned flags, void *ws, size_t ws_bytes,
+                           int64_t *d_info, cholmod_stream_t stream);
 
 /*
  * Batched modification of many independent factors (uneven n, k, sigma and
  * storage type) on one stream.  Each factor is modified exactly as by the
  * single-factor entry point of its storage type (same blocking, same
- * operations), so its result is bit for bit the one it gets alone.  The
- * batch runs as one preparation launch plus one launch per step, where
- * step s processes block s of every factor that has one (longest factor
- * first); the blocks of different factors run concurrently.
+ * operations), so its result is bit for bit the one it gets alone (with the
+ * default flags, or with CHOLMOD_FLAG_ROTATIONS under a plan without block
+ * maps).  By default the batch runs as one preparation launch and one
+ * persistent launch whose workgroups take the factors' owner items longest
+ * factor first (see the launch plans below); the blocks of different
+ * factors run concurrently.
  *   descs     HOST array of `count` descriptors (read during the call only);
  *             the factors must not overlap in memory
  *   count     0 .. 65535 (0 is a no-op)
@@ -218,9 +235,9 @@ int cholmod_update_batched(const cholmod_desc *descs, int64_t count, void *ws, s
                            int64_t *d_info, cholmod_stream_t stream);
 
 /*
- * Launch plans of batches.  A batch runs under one of two schedules, the
- * same per-element operations either way (every result is bit for bit the
- * single-factor one):
+ * Launch plans of batches.  A batch runs under one of two schedules (every
+ * result is bit for bit the single-factor one: with block maps as the
+ * default single-factor call, without as CHOLMOD_FLAG_ROTATIONS):
  *   CHOLMOD_SCHED_QUEUED   one preparation launch and one persistent launch
  *                          whose workgroups take owner items (the columns
  *                          of block j of factor f, every 16-column pass)
@@ -236,7 +253,7 @@ int cholmod_update_batched(const cholmod_desc *descs, int64_t count, void *ws, s
  * dominant (storage type, n bucket, k bucket) -- the bucket with most of
  * the batch's work, n^2 k summed over its factors; n buckets end at 256,
  * 1024, 4096, 16384 (bucket 4: larger), k buckets at 16, 32, 64 (bucket 3:
- * larger).  The table starts with {QUEUED, 0, BLOCK, 2} everywhere and is
+ * larger).  The table starts with {QUEUED, 0, BLOCK, 2, maps 1} everywhere and is
  * filled by cholmod_set_plan, normally from the plan cache of the
  * library's autotuner (paper_1011_1173_amd/tune.py), which times the
  * candidate plans of each bucket on the GPU.  The served mode uses the
@@ -252,6 +269,8 @@ typedef struct cholmod_plan {
   int32_t grid;      /* queued: persistent workgroups, 0 = one per compute unit (<= 65536) */
   int32_t order;     /* queued: CHOLMOD_ORDER_* */
   int32_t poll;      /* queued: 0, 1 or 2 */
+  int32_t maps;      /* queued: 1 = far blocks by their block maps, 0 = every block by its
+                        rotations (the stepped schedule always uses rotations) */
 } cholmod_plan;
 
 /* cholmod_update_batched with an explicit plan (NULL: the table's plan).

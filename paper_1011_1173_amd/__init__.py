@@ -116,13 +116,15 @@ class Pending:
 
 
 def update_async(L: torch.Tensor, V: torch.Tensor, sigma: int, *, exact: bool = False,
-                 blocked: bool = False, stream=None, workspace: torch.Tensor | None = None,
+                 blocked: bool = False, rotations: bool = False, stream=None,
+                 workspace: torch.Tensor | None = None,
                  info: torch.Tensor | None = None) -> Pending:
     """Enqueue the rank-k modification of L on ``stream``; no host sync.
 
     float64 tensors use cholmod_update_ex (``exact`` / ``blocked`` select the
     evaluation mode and schedule); float32 tensors use the FP32-storage mode
-    cholmod_update_f32s_async, which has neither option.
+    cholmod_update_f32s_ex, which has neither option.  ``rotations``: apply
+    every block by its rotations (no block maps) in the fast schedule.
     """
     n, k, ldl, V = _factor_args(L, V)
     f32 = L.dtype == torch.float32
@@ -138,24 +140,26 @@ def update_async(L: torch.Tensor, V: torch.Tensor, sigma: int, *, exact: bool = 
     args = (ctypes.c_void_p(L.data_ptr()), ctypes.c_void_p(V.data_ptr()), n, k, ldl, int(sigma))
     tail = (ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
             ctypes.c_void_p(info.data_ptr()), _stream_handle(stream))
+    rot = _native.FLAG_ROTATIONS if rotations else 0
     if f32:
-        st = lib.cholmod_update_f32s_async(*args, *tail)
+        st = lib.cholmod_update_f32s_ex(*args, rot, *tail)
     else:
-        flags = (FLAG_EXACT if exact else 0) | (FLAG_BLOCKED if blocked else 0)
+        flags = (FLAG_EXACT if exact else 0) | (FLAG_BLOCKED if blocked else 0) | rot
         st = lib.cholmod_update_ex(*args, flags, *tail)
     _raise_for(st)
     return Pending(k, workspace, info, stream)
 
 
 def update(L: torch.Tensor, V: torch.Tensor, sigma: int, *, exact: bool = False,
-           blocked: bool = False, stream=None) -> None:
+           blocked: bool = False, rotations: bool = False, stream=None) -> None:
     """Overwrite L (upper, on the GPU; float64, or float32 for FP32 storage)
     with the factor of L^T L + sigma V V^T.
 
     Raises NotPositiveDefinite / BadDiagonal with the first failing (row,
     column), or ArgumentError for bad shapes and types.
     """
-    update_async(L, V, sigma, exact=exact, blocked=blocked, stream=stream).wait()
+    update_async(L, V, sigma, exact=exact, blocked=blocked, rotations=rotations,
+                 stream=stream).wait()
 
 
 def workspace_bytes_ooc(n: int, k: int, dtype: int = F64) -> int:
@@ -267,7 +271,8 @@ def update_batched_async(Ls, Vs, sigmas, *, stream=None, workspace: torch.Tensor
         info = torch.empty(count, dtype=torch.int64, device=dev)
     if plan is not None and not isinstance(plan, _native.Plan):
         plan = _native.Plan(int(plan.get("schedule", 0)), int(plan.get("grid", 0)),
-                            int(plan.get("order", 0)), int(plan.get("poll", 2)))
+                            int(plan.get("order", 0)), int(plan.get("poll", 2)),
+                            int(plan.get("maps", 1)))
     st = lib.cholmod_update_batched_plan(arr, count,
                                          ctypes.byref(plan) if plan is not None else None,
                                          ctypes.c_void_p(workspace.data_ptr()),

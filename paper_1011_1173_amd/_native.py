@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcholmod_mi355x.so")
 
 OK, ERR_ARG, ERR_NOT_PD, ERR_BAD_DIAG, ERR_HIP = 0, -1, -2, -3, -4
-FLAG_EXACT, FLAG_BLOCKED = 1, 2
+FLAG_EXACT, FLAG_BLOCKED, FLAG_ROTATIONS = 1, 2, 4
 F64, F32S = 0, 1
 INFO_NONE = (1 << 63) - 1
 
@@ -28,7 +28,7 @@ EXPORTS = (
     "cholmod_server_poll", "cholmod_server_drain", "cholmod_server_destroy",
     "cholmod_noalloc_max_bytes", "cholmod_update_noalloc", "cholmod_probe_latency",
     "cholmod_update_batched_plan", "cholmod_set_plan", "cholmod_get_plan", "cholmod_plan_bucket",
-    "cholmod_compute_units",
+    "cholmod_compute_units", "cholmod_update_f32s_ex",
 )
 
 SCHED_QUEUED, SCHED_STEPPED = 0, 1
@@ -46,7 +46,7 @@ class ServerCfg(ctypes.Structure):
 class Plan(ctypes.Structure):
     """struct cholmod_plan of the header."""
     _fields_ = [("schedule", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("poll", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("poll", ctypes.c_int32), ("maps", ctypes.c_int32)]
 
 
 class Desc(ctypes.Structure):
@@ -96,6 +96,8 @@ def load():
     lib.cholmod_update_f32s.restype = ci
     lib.cholmod_update_f32s_async.argtypes = [p, p, i64, i64, i64, ci, p, sz, p, p]
     lib.cholmod_update_f32s_async.restype = ci
+    lib.cholmod_update_f32s_ex.argtypes = [p, p, i64, i64, i64, ci, ctypes.c_uint, p, sz, p, p]
+    lib.cholmod_update_f32s_ex.restype = ci
     lib.cholmod_workspace_bytes_ooc.argtypes = [i64, i64, ci]
     lib.cholmod_workspace_bytes_ooc.restype = sz
     lib.cholmod_update_ooc.argtypes = [p, p, i64, i64, i64, ci, ci, p, sz,

@@ -23,9 +23,11 @@ namespace chm {
 hipError_t run_blocked(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
                        double sg, Coef* T, int64_t* info, int64_t* stop, bool exact);
 hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
-                      double sg, Coef* T, int64_t* info, int64_t* stop, int32_t* flags);
+                      double sg, Coef* T, int64_t* info, int64_t* stop, int32_t* tickets,
+                      double* maps, int32_t* mstate);
 hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, float* W, int64_t k,
-                          double sg, void* T, int64_t* info, int64_t* stop, int32_t* flags);
+                          double sg, void* T, int64_t* info, int64_t* stop, int32_t* tickets,
+                          double* maps, int32_t* mstate);
 hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
                             const BatchEntry* d_ent, const BatchStep* steps, int64_t nsteps);
 hipError_t run_sysblk_batch_prepare(hipStream_t st, const BatchFactor* d_fac, int64_t count);
@@ -52,14 +54,19 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 //                    for each 16-column pass of the fast schedule)
 //   F                int32 ticket counters (the first one is the fast
 //                    schedule's work counter)
+//   M                (with maps) the fast schedule's block maps: 76 x 64
+//                    doubles per block and 16-column pass
+//   S                (with maps) one int32 state per block map
 struct WsLayout {
-  size_t ctrl = 0, w = 0, t = 0, f = 0, total = 0;
-  int64_t nflags = 0;
+  size_t ctrl = 0, w = 0, t = 0, f = 0, m = 0, s = 0, total = 0;
+  int64_t nflags = 0, nmaps = 0;
 };
+
+constexpr size_t kMapBytes = 76 * 64 * sizeof(double);
 
 bool mul_ok(int64_t a, int64_t b, int64_t lim) { return a == 0 || b <= lim / a; }
 
-bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out) {
+bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out, bool maps = true) {
   if (n < 0 || k < 0) return false;
   if (dtype != CHOLMOD_F64 && dtype != CHOLMOD_F32S) return false;
   const int64_t lim = INT64_MAX / 64;
@@ -75,7 +82,10 @@ bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out) {
   if (kp < 16) kp = 16;
   L.f = L.t + align_up((size_t)(n * kp) * sizeof(Coef));
   L.nflags = (k + 15) / 16;
-  L.total = L.f + align_up((size_t)L.nflags * sizeof(int32_t));
+  L.m = L.f + align_up((size_t)L.nflags * sizeof(int32_t));
+  L.nmaps = maps ? L.nflags * ((n + 63) / 64) : 0;
+  L.s = L.m + (size_t)L.nmaps * kMapBytes;
+  L.total = L.s + align_up((size_t)L.nmaps * sizeof(int32_t));
   *out = L;
   return true;
 }
@@ -109,7 +119,8 @@ int enqueue_f64(double* L, const double* V, int64_t n, int64_t k, int64_t ldl, i
                 unsigned flags, void* ws, size_t ws_bytes, int64_t* d_info, hipStream_t st) {
   int v = validate(L, V, n, k, ldl, sigma);
   if (v) return v;
-  if (flags & ~(unsigned)(CHOLMOD_FLAG_EXACT | CHOLMOD_FLAG_BLOCKED)) return CHOLMOD_ERR_ARG;
+  if (flags & ~(unsigned)(CHOLMOD_FLAG_EXACT | CHOLMOD_FLAG_BLOCKED | CHOLMOD_FLAG_ROTATIONS))
+    return CHOLMOD_ERR_ARG;
   if (d_info == nullptr) return CHOLMOD_ERR_ARG;
   if (((uintptr_t)d_info & 7u) != 0) return CHOLMOD_ERR_ARG;
   WsLayout lay;
@@ -136,15 +147,19 @@ int enqueue_f64(double* L, const double* V, int64_t n, int64_t k, int64_t ldl, i
   if (blocked) {
     e = run_blocked(st, L, n, ldl, W, k, sg, T, d_info, stop_row, exact);
   } else {
-    e = run_sysblk(st, L, n, ldl, W, k, sg, T, d_info, stop_row, F);
+    const bool maps = (flags & CHOLMOD_FLAG_ROTATIONS) == 0 && lay.nmaps > 0;
+    e = run_sysblk(st, L, n, ldl, W, k, sg, T, d_info, stop_row, F,
+                   maps ? (double*)(base + lay.m) : nullptr,
+                   maps ? (int32_t*)(base + lay.s) : nullptr);
   }
   return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
 }
 
 int enqueue_f32s(float* L, const float* V, int64_t n, int64_t k, int64_t ldl, int sigma,
-                 void* ws, size_t ws_bytes, int64_t* d_info, hipStream_t st) {
+                 unsigned flags, void* ws, size_t ws_bytes, int64_t* d_info, hipStream_t st) {
   int v = validate(L, V, n, k, ldl, sigma);
   if (v) return v;
+  if (flags & ~(unsigned)CHOLMOD_FLAG_ROTATIONS) return CHOLMOD_ERR_ARG;
   if (d_info == nullptr) return CHOLMOD_ERR_ARG;
   if (((uintptr_t)d_info & 7u) != 0) return CHOLMOD_ERR_ARG;
   WsLayout lay;
@@ -164,7 +179,10 @@ int enqueue_f32s(float* L, const float* V, int64_t n, int64_t k, int64_t ldl, in
                      stop_row, F, lay.nflags);
   if (hipGetLastError() != hipSuccess) return CHOLMOD_ERR_HIP;
   if (n == 0 || k == 0) return CHOLMOD_OK;
-  hipError_t e = run_sysblk_f32(st, L, n, ldl, W, k, (double)sigma, T, d_info, stop_row, F);
+  const bool maps = (flags & CHOLMOD_FLAG_ROTATIONS) == 0 && lay.nmaps > 0;
+  hipError_t e = run_sysblk_f32(st, L, n, ldl, W, k, (double)sigma, T, d_info, stop_row, F,
+                                maps ? (double*)(base + lay.m) : nullptr,
+                                maps ? (int32_t*)(base + lay.s) : nullptr);
   return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
 }
 
@@ -263,7 +281,7 @@ struct BatchPlan {
   std::vector<BatchStep> steps;
   std::vector<QItem> items;
   size_t off_ent = 0, off_items = 0, off_ticket = 0, off_left = 0, table_bytes = 0, total = 0;
-  std::vector<size_t> off_ctrl, off_w, off_t;
+  std::vector<size_t> off_ctrl, off_w, off_t, off_m, off_s;  // off_m, off_s: 0 = no maps
 };
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -278,7 +296,8 @@ int validate_desc(const cholmod_desc& d) {
 // the same operations in the same order), so every factor's result is the
 // one it gets alone.
 int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P,
-               bool queued = true, int order = CHOLMOD_ORDER_BLOCK) {
+               bool queued = true, int order = CHOLMOD_ORDER_BLOCK, bool maps = true) {
+  maps = maps && queued;  // the per-step schedule applies every block by rotations
   if (count < 0 || count > kMaxBatch) return CHOLMOD_ERR_ARG;
   if (count > 0 && descs == nullptr) return CHOLMOD_ERR_ARG;
   P->queued = queued;
@@ -308,13 +327,19 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P,
   P->off_ctrl.resize(count);
   P->off_w.resize(count);
   P->off_t.resize(count);
+  P->off_m.assign(count, 0);
+  P->off_s.assign(count, 0);
   for (int64_t f = 0; f < count; ++f) {
     const cholmod_desc& d = descs[f];
     WsLayout lay;
-    if (!layout_for(d.n, d.k, d.dtype, &lay)) return CHOLMOD_ERR_ARG;
+    if (!layout_for(d.n, d.k, d.dtype, &lay, maps)) return CHOLMOD_ERR_ARG;
     P->off_ctrl[f] = off + lay.ctrl;
     P->off_w[f] = off + lay.w;
     P->off_t[f] = off + lay.t;
+    if (lay.nmaps > 0) {
+      P->off_m[f] = off + lay.m;
+      P->off_s[f] = off + lay.s;
+    }
     off += lay.total;
   }
   P->total = off;
@@ -332,6 +357,8 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P,
     F.stop = (int64_t*)(ws + P->off_ctrl[f]);
     F.left = queued ? (int32_t*)(ws + P->off_left) + f : nullptr;
     F.done = nullptr;  // set by a caller that wants per-factor completion
+    F.maps = P->off_m[f] ? (void*)(ws + P->off_m[f]) : nullptr;
+    F.mstate = P->off_s[f] ? (int32_t*)(ws + P->off_s[f]) : nullptr;
     F.n = d.n;
     F.k = d.k;
     F.ldl = d.ldl;
@@ -461,6 +488,7 @@ cholmod_plan default_plan() {
   p.grid = 0;
   p.order = CHOLMOD_ORDER_BLOCK;
   p.poll = 2;
+  p.maps = 1;
   return p;
 }
 
@@ -485,7 +513,7 @@ bool plan_ok(const cholmod_plan& p) {
   return (p.schedule == CHOLMOD_SCHED_QUEUED || p.schedule == CHOLMOD_SCHED_STEPPED) &&
          p.grid >= 0 && p.grid <= 65536 &&
          (p.order == CHOLMOD_ORDER_BLOCK || p.order == CHOLMOD_ORDER_FACTOR) && p.poll >= 0 &&
-         p.poll <= 2;
+         p.poll <= 2 && (p.maps == 0 || p.maps == 1);
 }
 
 // The table's plan for a batch (descriptors already validated).
@@ -514,14 +542,14 @@ int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_
   const cholmod_plan lp = plan ? *plan : default_plan();
   if (!plan_ok(lp)) return CHOLMOD_ERR_ARG;
   const bool queued = after_step == nullptr && lp.schedule == CHOLMOD_SCHED_QUEUED;
-  int rc = plan_batch(descs, count, nullptr, &P, queued, lp.order);
+  int rc = plan_batch(descs, count, nullptr, &P, queued, lp.order, lp.maps != 0);
   if (rc) return rc;
   if (count == 0) return CHOLMOD_OK;
   if (d_info == nullptr || ((uintptr_t)d_info & 7u) != 0) return CHOLMOD_ERR_ARG;
   if (ws == nullptr || ws_bytes < P.total || ((uintptr_t)ws % kAlign) != 0)
     return CHOLMOD_ERR_ARG;
   if (stage == nullptr || stage_bytes < P.table_bytes) return CHOLMOD_ERR_ARG;
-  rc = plan_batch(descs, count, (char*)ws, &P, queued, lp.order);
+  rc = plan_batch(descs, count, (char*)ws, &P, queued, lp.order, lp.maps != 0);
   if (rc) return rc;
   P.grid = lp.grid;
   P.poll = lp.poll;
@@ -984,7 +1012,13 @@ int cholmod_update_noalloc(double* L, const double* V, int64_t n, int64_t k, int
 int cholmod_update_f32s_async(float* L, const float* V, int64_t n, int64_t k, int64_t ldl,
                               int sigma, void* ws, size_t ws_bytes, int64_t* d_info,
                               cholmod_stream_t stream) {
-  return enqueue_f32s(L, V, n, k, ldl, sigma, ws, ws_bytes, d_info, (hipStream_t)stream);
+  return enqueue_f32s(L, V, n, k, ldl, sigma, 0u, ws, ws_bytes, d_info, (hipStream_t)stream);
+}
+
+int cholmod_update_f32s_ex(float* L, const float* V, int64_t n, int64_t k, int64_t ldl,
+                           int sigma, unsigned flags, void* ws, size_t ws_bytes, int64_t* d_info,
+                           cholmod_stream_t stream) {
+  return enqueue_f32s(L, V, n, k, ldl, sigma, flags, ws, ws_bytes, d_info, (hipStream_t)stream);
 }
 
 int cholmod_update_f32s(float* L, const float* V, int64_t n, int64_t k, int64_t ldl, int sigma,
@@ -993,7 +1027,7 @@ int cholmod_update_f32s(float* L, const float* V, int64_t n, int64_t k, int64_t 
   if (v) return v;
   return run_sync(n, k, CHOLMOD_F32S, (hipStream_t)stream,
                   [&](void* ws, size_t bytes, int64_t* d_info, hipStream_t st) {
-                    return enqueue_f32s(L, V, n, k, ldl, sigma, ws, bytes, d_info, st);
+                    return enqueue_f32s(L, V, n, k, ldl, sigma, 0u, ws, bytes, d_info, st);
                   });
 }
 
@@ -1025,7 +1059,8 @@ int cholmod_batch_graph_create(const cholmod_desc* descs, int64_t count, void* w
   if (ws == nullptr || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return CHOLMOD_ERR_ARG;
   const cholmod_plan lp = select_plan(descs, count);
   BatchPlan P;
-  int rc = plan_batch(descs, count, (char*)ws, &P, lp.schedule == CHOLMOD_SCHED_QUEUED, lp.order);
+  int rc = plan_batch(descs, count, (char*)ws, &P, lp.schedule == CHOLMOD_SCHED_QUEUED, lp.order,
+                      lp.maps != 0);
   if (rc) return rc;
   P.grid = lp.grid;
   P.poll = lp.poll;

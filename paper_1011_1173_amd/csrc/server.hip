@@ -7,7 +7,7 @@
 // forms a batch from the waiting requests, oldest first, at most one per
 // factor and none of a factor whose previous request is still running (a
 // factor's requests run in submission order), taking each request whose
-// workspace (its private copy of V and its rotation records) still fits
+// workspace (its private copy of V, its rotation records and block maps) still fits
 // into the free part of the arena; a request that could not fit even into
 // an empty arena fails with CHOLMOD_ERR_ARG.  The batch takes its arena
 // range, one of the server's streams and runs as one persistent launch (the

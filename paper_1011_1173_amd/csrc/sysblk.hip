@@ -58,6 +58,8 @@
 // form's launches for later blocks and passes skip the rows at or after
 // it; the owner schedule simply carries on (every later value is
 // unspecified) and the first failure stays the reported one.
+#include <type_traits>
+
 #include "rotations.h"
 #include "batch.h"
 
@@ -127,6 +129,8 @@ struct SbLds {
   int tmo;                  // owner schedule: a wait ran out of time
   int cnt[2][4];            // owner schedule: rows of each 16-row window of the applied
                             // block staged, by round parity
+  int mfl[2];               // owner schedule: state of the applied block's map, by block
+                            // parity
 };
 
 // Row shift by D lanes within each 16-lane row (DPP row_shr:D); the first D
@@ -391,6 +395,206 @@ __device__ __forceinline__ void apply2x2(SbLds& sh, ST* tile, int kc_, int lt,
   RotRec qa[2] = {rp[0], rp[1]};
   int s = 0;
   sub2x2_run<SG, ST, LD>(tile, rp, s, S, h, c0, hf, first, w, xin, qa);
+}
+
+// ------------------------------------------------------------- block maps
+// The Apply of one block (its 64 rows, kc <= 16 rotations each) to a column
+// of the trailing matrix changes only the column's 64 entries in the block's
+// rows and the column's 16 values of V (Algorithm 1, Apply), and it is
+// linear in those 80 values with the same coefficients for every column: the
+// block acts on each column as one 80 x 80 matrix, its map.  For an update
+// the map is orthogonal (with 1/c and s/c as cosine and sine each rotation
+// is a plane rotation); for a downdate it is a product of hyperbolic
+// rotations.  An owner far behind the chain applies a block by its map -- a
+// product of the map with the owner's 80 x 64 tile (64 rows of L, 16 rows of
+// V) on the FP64 matrix cores -- instead of by the block's 1024 rotations
+// one after the other; the workgroup that ran the block's chain builds the
+// map once, by applying the block's rotations to the 80 unit vectors.
+//
+// The map's top-left 64 x 64 part is lower triangular (entry r of a column's
+// result depends only on its entries <= r and on V), so 19 of its 25 16 x 16
+// tiles are stored: the A operands of the v_mfma_f64_16x16x4 products that
+// use them, 64 doubles each in lane order (lane l holds row l % 16, k index
+// l / 16 of its operand), by row tile I (0..3: rows of L, 4: rows of V), then
+// k-step.  The k-steps of row tile I < 4 are those of columns [0, 16 I + 16)
+// of L and then the four of V; row tile 4 takes all 20.  k-step K, k index g
+// is column 4 K + g of the 80 (rows of L, then of V): lane l of a product's
+// output holds rows 4 r + l / 16 (r = 0..3) of column l % 16, which for row
+// tile 4 is exactly the V operand the next block's k-steps 16 + r need from
+// that lane, so V stays in registers from block to block.
+//
+// A map with an entry beyond kMapBound in magnitude (a downdate whose
+// hyperbolic rotations grow vectors, or a block with a failed row) is marked
+// unusable, and every owner applies that block by its rotations.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kMapPairs = 76;                // (row tile, k-step) operands stored
+constexpr int kMapElems = kMapPairs * 64;    // doubles per map
+constexpr int kLdM = kBR + kKP;              // row stride of the map being built
+constexpr int kMapLanes = kLdM / 4 * 16;     // apply lanes of the build: 320
+constexpr double kMapBound = 2.0;
+constexpr int kNear = 3;                     // blocks before an owner's own applied by rotations
+enum : int32_t { kMapNone = 0, kMapOk = 1, kMapRot = 2 };
+
+__host__ __device__ constexpr int map_base(int I) {
+  return I == 0 ? 0 : I == 1 ? 8 : I == 2 ? 20 : I == 3 ? 36 : 56;
+}
+// k-steps of row tile I that take columns of L
+__host__ __device__ constexpr int map_lk(int I) { return I < 4 ? 4 * (I + 1) : 16; }
+
+// Row of the map and column (of the 80) of operand element (pair e, lane l).
+__device__ __forceinline__ void map_entry(int e, int l, int& row, int& col) {
+  const int I = e < 8 ? 0 : e < 20 ? 1 : e < 36 ? 2 : e < 56 ? 3 : 4;
+  const int kl = e - map_base(I), g = l >> 4;
+  row = 16 * I + (l & 15);
+  col = kl < map_lk(I) ? 4 * kl + g : kBR + 4 * (kl - map_lk(I)) + g;
+}
+
+// Build the map of the block whose records are in sh.R (after its chain) and
+// publish it: the 64 x 80 unit tile (its columns the unit vectors of the
+// block's rows, then of V's rows) goes through the block's rotations on
+// apply lanes 0 .. 319, the result is written in operand order with
+// device-scope stores, and the map's state (usable or not) is stored after a
+// device-scope fence.  Uses sh.Lh and sh.Hb; all threads of the workgroup.
+template <int SG, int KCF>
+__device__ __forceinline__ void map_build(SbLds& sh, int kc, double* __restrict__ Mg,
+                                          int32_t* __restrict__ state) {
+  const int tid = threadIdx.x;
+  double* const tile = &sh.Lh[0][0];  // 64 x 80
+  double* const vm = &sh.Hb[0][0][0];  // 16 x 80: V's rows of the result
+  for (int idx = tid; idx < kBR * kLdM; idx += kThreads)
+    tile[idx] = (idx / kLdM == idx % kLdM) ? 1.0 : 0.0;
+  __syncthreads();
+  if (tid < kMapLanes) {
+    double w[kOwnCols];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        w[2 * k + u] = own_col(tid, u) - kBR == own_rot(tid, k) ? 1.0 : 0.0;
+    apply2x2<SG, double, KCF, kLdM>(sh, tile, kc, tid, w);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) vm[own_rot(tid, k) * kLdM + own_col(tid, u)] = w[2 * k + u];
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int idx = tid; idx < kMapElems; idx += kThreads) {
+    int row, col;
+    map_entry(idx >> 6, idx & 63, row, col);
+    const double v = row < kBR ? tile[row * kLdM + col] : vm[(row - kBR) * kLdM + col];
+    bad |= !(__builtin_fabs(v) <= kMapBound);
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(Mg + idx), __builtin_bit_cast(uint64_t, v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __threadfence();  // every thread's map stores, device-wide, before the state
+  const int anybad = __syncthreads_or(bad);
+  if (tid == 0)
+    __hip_atomic_store(state, anybad ? (int32_t)kMapRot : (int32_t)kMapOk, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait for a map's state (one thread): kMapOk or kMapRot; a wait that runs
+// past the deadline sets sh.tmo and reports kMapRot.
+__device__ __forceinline__ int map_wait(SbLds& sh, const int32_t* state, int64_t deadline) {
+  for (;;) {
+    const int v = __hip_atomic_load(const_cast<int32_t*>(state), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    if (v != kMapNone) return v;
+    if (wall_clock64() > deadline) {
+      sh.tmo = 1;
+      return kMapRot;
+    }
+    __builtin_amdgcn_s_sleep(20);
+  }
+}
+
+__device__ __forceinline__ double map_ld(const double* p) {
+  return __builtin_bit_cast(double, __hip_atomic_load(reinterpret_cast<uint64_t*>(
+                                                          const_cast<double*>(p)),
+                                                      __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Stage map Mb into LDS at dst (wave q of the four staging waves copies
+// doubles [q * 1216, q * 1216 + 1216)), after waiting for the map's state,
+// which every staging wave reads for itself; returns the state (the map is
+// copied only if it is usable).
+constexpr int kMapPerWave = kMapElems / 4;  // 1216 = 19 x 64
+__device__ __forceinline__ int map_stage(SbLds& sh, const double* Mb, const int32_t* state,
+                                         double* dst, int64_t deadline, int q, int lane) {
+  int st = 0;
+  if (lane == 0) st = map_wait(sh, state, deadline);
+  st = __builtin_amdgcn_readfirstlane(st);
+  if (st == kMapOk) {
+    double v[kMapPerWave / 64];
+#pragma unroll
+    for (int i = 0; i < kMapPerWave / 64; ++i) v[i] = map_ld(Mb + q * kMapPerWave + i * 64 + lane);
+#pragma unroll
+    for (int i = 0; i < kMapPerWave / 64; ++i) dst[q * kMapPerWave + i * 64 + lane] = v[i];
+  }
+  return st;
+}
+
+// B operands of the owner's tile (rows [pb, pb + 64), columns 16 ct ..
+// 16 ct + 15 of those from pj, the first bbc in the factor) for one wave:
+// bx[K] = row 4 K + lane / 16, column lane % 16.
+template <typename ST>
+__device__ __forceinline__ void map_tile_load(double (&bx)[16], const ST* __restrict__ L,
+                                              int64_t ldl, int64_t pb, int64_t pj, int bbc,
+                                              int ct, int lane) {
+  const int g = lane >> 4, cl = 16 * ct + (lane & 15);
+  const bool ok = cl < bbc;
+#pragma unroll
+  for (int K = 0; K < 16; ++K) bx[K] = ok ? (double)L[(pb + 4 * K + g) * ldl + pj + cl] : 0.0;
+}
+
+template <int I>
+__device__ __forceinline__ void map_rows(const double* Mb, int lane, const double (&bx)[16],
+                                         const double (&vx)[4], v4d& acc) {
+  constexpr int nk = map_lk(I);
+#pragma unroll
+  for (int K = 0; K < nk; ++K)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Mb[(map_base(I) + K) * 64 + lane], bx[K], acc, 0,
+                                               0, 0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Mb[(map_base(I) + nk + q) * 64 + lane], vx[q],
+                                               acc, 0, 0, 0);
+}
+
+// Apply the map staged in LDS at Mb to the wave's 16 columns of the owner's
+// tile, whose B operands are in bx (map_tile_load), one wave; the result
+// rows go to L, and vx (V of those columns: lane l, element r is row
+// 4 r + l / 16 of V, column l % 16) is updated in place.
+template <typename ST>
+__device__ __forceinline__ void map_apply(const double* Mb, const double (&bx)[16],
+                                          ST* __restrict__ L, int64_t ldl, int64_t pb,
+                                          int64_t pj, int bbc, int ct, int lane,
+                                          double (&vx)[4]) {
+  const int g = lane >> 4, cl = 16 * ct + (lane & 15);
+  // one row tile after the other (V's last, vx is an input of all five),
+  // each stored at once, so that few accumulators and operands are live
+  // (the scheduling barriers keep the compiler from hoisting every operand
+  // load of the block)
+  auto rows = [&](auto I_, v4d& acc) {
+    constexpr int I = decltype(I_)::value;
+    acc = (v4d){0.0, 0.0, 0.0, 0.0};
+    map_rows<I>(Mb, lane, bx, vx, acc);
+    if (I < 4 && cl < bbc) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) L[(pb + 16 * I + 4 * r + g) * ldl + pj + cl] = (ST)acc[r];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  v4d a, b;
+  rows(std::integral_constant<int, 0>{}, a);
+  rows(std::integral_constant<int, 1>{}, b);
+  rows(std::integral_constant<int, 2>{}, a);
+  rows(std::integral_constant<int, 3>{}, b);
+  rows(std::integral_constant<int, 4>{}, a);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) vx[r] = a[r];
 }
 
 // ------------------------------------------------------------------ chain
@@ -1086,16 +1290,43 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
 }
 
 // One factor as the owner kernels see it.  Pass p (columns 16p .. of V)
-// keeps its records at T + p * n * 16.
+// keeps its records at T + p * n * 16 and the maps of its blocks at
+// maps + p * nb * kMapElems, their states at mstate + p * nb (nb blocks);
+// maps == nullptr: every block is applied by its rotations.
 template <typename ST>
 struct OwnF {
   ST* L;
   const ST* W;  // private copy of V, row stride k
   GRec<ST>* T;
+  double* maps;
+  int32_t* mstate;
   int64_t* info;
   int64_t* stop;
   int64_t n, k, ldl;
 };
+
+// V of apply lane tid's columns from rows m of buf[m * 64 + c] (the 16 x 64
+// staging area in sh.Hb) and back: how V moves between the map layout and
+// the rotation layout.
+template <typename ST>
+__device__ __forceinline__ void w_from_lds(ST (&w)[kOwnCols], const double* buf, int kc,
+                                           int bbc, int tid) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int c = own_col(tid, u), m = own_rot(tid, k);
+      w[2 * k + u] = (c < bbc && m < kc) ? (ST)buf[m * kBR + c] : (ST)0;
+    }
+}
+
+template <typename ST>
+__device__ __forceinline__ void w_to_lds(const ST (&w)[kOwnCols], double* buf, int tid) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) buf[own_rot(tid, k) * kBR + own_col(tid, u)] = (double)w[2 * k + u];
+}
 
 // Pass `pass` of the owner of block j (the block's triangle is in sh.Lb):
 // apply blocks 0 .. j-1 of this pass to the block's columns as their owners
@@ -1111,24 +1342,122 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
   GRec<ST>* const T = F.T + (int64_t)pass * F.n * kKP;
   const ST* const W = F.W + m0;
   const int64_t ldw = F.k;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int64_t nb = (F.n + kBR - 1) / kBR;
+  // blocks [0, nfar) by their maps (the owners of blocks up to j - kNear - 1
+  // find them built: each is built right after its chain), the rest by
+  // their rotations
+  const int nfar = F.maps ? imax(0, j - kNear) : 0;
+  double* const maps = F.maps ? F.maps + (int64_t)pass * nb * kMapElems : nullptr;
+  int32_t* const mstate = F.maps ? F.mstate + (int64_t)pass * nb : nullptr;
+  double* const vbuf = &sh.Hb[0][0][0];  // 16 x 64: V between the two layouts
   // every global input of the pass is issued before anything is staged: V
   // of the block's columns and the first tile
   ST w[kOwnCols];
+  double vx[4];  // map layout (waves 0-3): row 4 r + lane / 16 of V, column 16 wv + lane % 16
+  if (nfar > 0) {
+    const int cl = 16 * wv + (lane & 15);
 #pragma unroll
-  for (int k = 0; k < 2; ++k)
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int c = own_col(tid, u), m = own_rot(tid, k);
-      w[2 * k + u] = (tid < kOwnThreads && c < bbc && m < kc) ? W[(pj + c) * ldw + m] : (ST)0;
+    for (int r = 0; r < 4; ++r) {
+      const int m = 4 * r + (lane >> 4);
+      vx[r] = (wv < 4 && cl < bbc && m < kc) ? (double)W[(pj + cl) * ldw + m] : 0.0;
     }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int c = own_col(tid, u), m = own_rot(tid, k);
+        w[2 * k + u] = (tid < kOwnThreads && c < bbc && m < kc) ? W[(pj + c) * ldw + m] : (ST)0;
+      }
+  }
   TileRegs<ST> tr;
-  if (j > 0) tile_issue_a(tr, F.L, F.ldl, 0, pj, bbc);
+  if (nfar == 0 && j > 0) tile_issue_a(tr, F.L, F.ldl, 0, pj, bbc);
   // identity records everywhere: the pad rows keep them, each block's rows
-  // are overwritten as they arrive
-  for (int idx = tid; idx < kRRows * kKP; idx += kThreads) sh.R[idx >> 4][idx & 15] = identity_rec();
+  // are overwritten as they arrive (after the far blocks, whose maps are
+  // staged where the records go)
+  if (nfar == 0)
+    for (int idx = tid; idx < kRRows * kKP; idx += kThreads) sh.R[idx >> 4][idx & 15] = identity_rec();
   __syncthreads();
   chain_setup_tri(sh, bbc);  // needs only the triangle: done before the applies
-  for (int b = 0; b < j; ++b) {
+  if (nfar > 0) {
+    // Far blocks: waves 0-3 multiply block b's map (staged in LDS buffer
+    // b & 1) into their columns while waves 4-7 stage the map of block b+1
+    // into the other buffer; each wave 0-3 loads its B operands of block
+    // b+1 during block b's products.  A map that is not usable makes the
+    // workgroup apply that block by its rotations.
+    // map buffer of block b: the apply tile's region for even b, the
+    // records' for odd b
+    auto mbuf = [&](int b) -> double* { return (b & 1) ? &sh.R[0][0].c : &sh.Lh[0][0]; };
+    double bx[16];
+    if (wv >= 4) {
+      const int st = map_stage(sh, maps, mstate, mbuf(0), deadline, wv - 4, lane);
+      if (wv == 4 && lane == 0) sh.mfl[0] = st;
+    } else {
+      map_tile_load<ST>(bx, F.L, F.ldl, 0, pj, bbc, wv, lane);
+    }
+    __syncthreads();
+    for (int b = 0; b < nfar; ++b) {
+      const int64_t pb = (int64_t)b * kBR;
+      const bool more = b + 1 < nfar;
+      if (sh.mfl[b & 1] == kMapOk) {
+        if (wv < 4) {
+          map_apply<ST>(mbuf(b), bx, F.L, F.ldl, pb, pj, bbc, wv, lane, vx);
+          if (more) map_tile_load<ST>(bx, F.L, F.ldl, pb + kBR, pj, bbc, wv, lane);
+        } else if (more) {
+          const int st = map_stage(sh, maps + (int64_t)(b + 1) * kMapElems, mstate + b + 1,
+                                   mbuf(b + 1), deadline, wv - 4, lane);
+          if (wv == 4 && lane == 0) sh.mfl[(b + 1) & 1] = st;
+        }
+        __syncthreads();
+      } else {
+        // by the block's rotations (the map buffers are free: block b+1's
+        // map is staged afterwards); V to the rotation layout and back
+        if (wv < 4) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) vbuf[(4 * r + (lane >> 4)) * kBR + 16 * wv + (lane & 15)] = vx[r];
+        }
+        for (int idx = tid; idx < kRRows * kKP; idx += kThreads)
+          sh.R[idx >> 4][idx & 15] = identity_rec();
+        TileRegs<ST> tf;
+        tile_issue_a(tf, F.L, F.ldl, pb, pj, bbc);
+        __syncthreads();
+        if (tid < kOwnThreads) w_from_lds(w, vbuf, kc, bbc, tid);
+        tile_stage(sh, tf);
+        __syncthreads();
+        owner_apply<SG, ST, KCF>(sh, kc, pb, w, T, deadline, false, poll);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kTilePerThread; ++q) {
+          const int idx = tid + q * kThreads, r = idx >> 6, c = idx & 63;
+          if (c < bbc) F.L[(pb + r) * F.ldl + pj + c] = tile_a<ST>(sh)[r * kLdA + c];
+        }
+        if (tid < kOwnThreads) w_to_lds(w, vbuf, tid);
+        __syncthreads();
+        if (wv < 4) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) vx[r] = vbuf[(4 * r + (lane >> 4)) * kBR + 16 * wv + (lane & 15)];
+          if (more) map_tile_load<ST>(bx, F.L, F.ldl, pb + kBR, pj, bbc, wv, lane);
+        } else if (more) {
+          const int st = map_stage(sh, maps + (int64_t)(b + 1) * kMapElems, mstate + b + 1,
+                                   mbuf(b + 1), deadline, wv - 4, lane);
+          if (wv == 4 && lane == 0) sh.mfl[(b + 1) & 1] = st;
+        }
+        __syncthreads();
+      }
+    }
+    // V to the rotation layout for the rest; the records get their identity
+    // pad rows back
+    if (wv < 4) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) vbuf[(4 * r + (lane >> 4)) * kBR + 16 * wv + (lane & 15)] = vx[r];
+    }
+    for (int idx = tid; idx < kRRows * kKP; idx += kThreads) sh.R[idx >> 4][idx & 15] = identity_rec();
+    if (j > nfar) tile_issue_a(tr, F.L, F.ldl, (int64_t)nfar * kBR, pj, bbc);
+    __syncthreads();
+    if (tid < kOwnThreads) w_from_lds(w, vbuf, kc, bbc, tid);
+  }
+  for (int b = nfar; b < j; ++b) {
     __syncthreads();  // sh.A is free again
     tile_stage(sh, tr);
     if (b + 1 < j) tile_issue_a(tr, F.L, F.ldl, (int64_t)(b + 1) * kBR, pj, bbc);
@@ -1159,6 +1488,11 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
     atomicMin((unsigned long long*)F.info,
               (unsigned long long)info_key(pj * F.k + m0, kCodeTimeout));
   __syncthreads();
+  // the block's map, for the owners of blocks j + kNear + 1 and later
+  if (F.maps && j + kNear + 1 < nb) {
+    map_build<SG, KCF>(sh, kc, maps + (int64_t)j * kMapElems, mstate + j);
+    __syncthreads();
+  }
 }
 
 // Every pass of the owner of block j.  The passes of one block run in order;
@@ -1212,6 +1546,8 @@ __device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int
   if (B.dtype == kStoreF64) {
     OwnF<double> F;
     F.L = (double*)B.L;
+    F.maps = (double*)B.maps;
+    F.mstate = B.mstate;
     F.W = (const double*)B.W;
     F.T = (GRec<double>*)B.T;
     F.info = B.info;
@@ -1224,6 +1560,8 @@ __device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int
   } else {
     OwnF<float> F;
     F.L = (float*)B.L;
+    F.maps = (double*)B.maps;
+    F.mstate = B.mstate;
     F.W = (const float*)B.W;
     F.T = (GRec<float>*)B.T;
     F.info = B.info;
@@ -1303,16 +1641,23 @@ __global__ void k_prepare_qbatch(const BatchFactor* __restrict__ fac,
     uint32_t* __restrict__ r = (uint32_t*)F.T;
     for (int64_t i = i0; i < rwords; i += stride) r[i] = RecBits<float>::kEmpty;
   }
+  // no block map is built yet
+  if (F.maps != nullptr) {
+    const int64_t nstate = passes * ((F.n + kBR - 1) / kBR);
+    for (int64_t i = i0; i < nstate; i += stride) F.mstate[i] = kMapNone;
+  }
 }
 
 // Records of one pass start out empty.
 template <typename ST>
-__global__ void k_owner_clear(GRec<ST>* __restrict__ T, int64_t words) {
+__global__ void k_owner_clear(GRec<ST>* __restrict__ T, int64_t words,
+                              int32_t* __restrict__ mstate, int64_t nstate) {
   using U = typename RecBits<ST>::U;
   U* __restrict__ p = reinterpret_cast<U*>(T);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
-    p[i] = RecBits<ST>::kEmpty;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < words; i += stride) p[i] = RecBits<ST>::kEmpty;
+  for (int64_t i = i0; i < nstate; i += stride) mstate[i] = kMapNone;
 }
 
 // ------------------------------------------------------- latency probes
@@ -1484,18 +1829,22 @@ int owner_grid_limit() {
 // out empty.
 template <typename ST>
 hipError_t run_sysblk_t(hipStream_t st, ST* L, int64_t n, int64_t ldl, ST* W, int64_t k, int sg,
-                        void* Tws, int64_t* info, int64_t* stop, int32_t* tickets) {
+                        void* Tws, int64_t* info, int64_t* stop, int32_t* tickets, double* maps,
+                        int32_t* mstate) {
   GRec<ST>* R = reinterpret_cast<GRec<ST>*>(Tws);
   const int64_t nb = (n + kBR - 1) / kBR;
   const int64_t passes = (k + kKP - 1) / kKP;
   const int64_t words = n * kKP * 4 * passes;
+  const int64_t nstate = maps ? passes * nb : 0;
   const int64_t cblocks = (words + 255) / 256;
   const unsigned cgrid = (unsigned)(cblocks < 4096 ? cblocks : 4096);
-  hipLaunchKernelGGL(k_owner_clear<ST>, dim3(cgrid), dim3(256), 0, st, R, words);
+  hipLaunchKernelGGL(k_owner_clear<ST>, dim3(cgrid), dim3(256), 0, st, R, words, mstate, nstate);
   OwnF<ST> F;
   F.L = L;
   F.W = W;
   F.T = R;
+  F.maps = maps;
+  F.mstate = mstate;
   F.info = info;
   F.stop = stop;
   F.n = n;
@@ -1559,16 +1908,21 @@ hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t co
 // pass.  W is the private copy of V (row stride k); T holds n x 16 records;
 // tickets holds one zeroed int32 per pass.
 hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
-                      double sg, Coef* T, int64_t* info, int64_t* stop, int32_t* tickets) {
-  return run_sysblk_t<double>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets);
+                      double sg, Coef* T, int64_t* info, int64_t* stop, int32_t* tickets,
+                      double* maps, int32_t* mstate) {
+  return run_sysblk_t<double>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets, maps,
+                              mstate);
 }
 
 // The same schedule with L, V and the records stored in FP32: the rows of a
 // block (Compute and the Apply inside the block) run in FP64 from the FP32
-// values, the Apply to other blocks' columns runs in FP32.
+// values; the Apply to other blocks' columns runs in FP32 by rotations, in
+// FP64 by block maps.
 hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, float* W, int64_t k,
-                          double sg, void* T, int64_t* info, int64_t* stop, int32_t* tickets) {
-  return run_sysblk_t<float>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets);
+                          double sg, void* T, int64_t* info, int64_t* stop, int32_t* tickets,
+                          double* maps, int32_t* mstate) {
+  return run_sysblk_t<float>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets, maps,
+                             mstate);
 }
 
 // Latency probes (see k_probe_chain, k_probe_handoff): out[0] ns per chain

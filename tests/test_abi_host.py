@@ -250,7 +250,8 @@ def test_plan_table_on_host(nat):
     assert lib.cholmod_plan_bucket(-1, 1, None, None) == nat.ERR_ARG
     p = nat.Plan()
     assert lib.cholmod_get_plan(nat.F64, 2, 1, ctypes.byref(p)) == nat.OK
-    keep = nat.Plan(p.schedule, p.grid, p.order, p.poll)
+    assert p.maps == 1  # the default plan applies far blocks by their maps
+    keep = nat.Plan(p.schedule, p.grid, p.order, p.poll, p.maps)
     q = nat.Plan(nat.SCHED_QUEUED, 128, nat.ORDER_FACTOR, 0)
     assert lib.cholmod_set_plan(nat.F64, 2, 1, ctypes.byref(q)) == nat.OK
     r = nat.Plan()
@@ -258,7 +259,7 @@ def test_plan_table_on_host(nat):
     assert (r.schedule, r.grid, r.order, r.poll) == (0, 128, 1, 0)
     assert lib.cholmod_set_plan(nat.F64, 2, 1, ctypes.byref(keep)) == nat.OK
     for bad in [nat.Plan(2, 0, 0, 2), nat.Plan(0, -1, 0, 2), nat.Plan(0, 0, 2, 2),
-                nat.Plan(0, 0, 0, 3)]:
+                nat.Plan(0, 0, 0, 3), nat.Plan(0, 0, 0, 2, 2)]:
         assert lib.cholmod_set_plan(nat.F64, 0, 0, ctypes.byref(bad)) == nat.ERR_ARG
     assert lib.cholmod_set_plan(7, 0, 0, ctypes.byref(q)) == nat.ERR_ARG
     assert lib.cholmod_set_plan(nat.F64, 5, 0, ctypes.byref(q)) == nat.ERR_ARG

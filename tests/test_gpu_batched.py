@@ -32,13 +32,13 @@ def to_dev(a, f32):
     return torch.from_numpy(np.ascontiguousarray(a.astype(np.float32 if f32 else np.float64))).cuda()
 
 
-def run_both(cases):
+def run_both(cases, rotations=False):
     """cases: [(L, V, sigma, f32)] -> (single results, batched results, batched statuses)."""
     import paper_1011_1173_amd as chm
     single, stat1 = [], []
     for L, V, sg, f32 in cases:
         Ld, Vd = to_dev(L, f32), to_dev(V, f32)
-        stat1.append(chm.update_async(Ld, Vd, sg).status())
+        stat1.append(chm.update_async(Ld, Vd, sg, rotations=rotations).status())
         single.append(Ld.cpu().numpy().astype(np.float64))
     Ls = [to_dev(L, f32) for L, _, _, f32 in cases]
     Vs = [to_dev(V, f32) for _, V, _, f32 in cases]
@@ -105,20 +105,28 @@ def test_batched_uneven_pool(orc):
 
 def test_every_tuned_plan_equals_single_bitwise(orc):
     """Every launch plan the autotuner may pick (stepped or queued; queued
-    with fewer workgroups, factor-major order, other poll levels) leaves each
-    factor of the mixed batch bit for bit where the single-factor path does."""
+    with fewer workgroups, factor-major order, other poll levels, with or
+    without block maps) leaves each factor of the mixed batch bit for bit
+    where the single-factor path does: the default single-factor path for a
+    queued plan with maps, the single-factor path with every block by its
+    rotations otherwise."""
     import paper_1011_1173_amd as chm
     from paper_1011_1173_amd import _native, tune
     cus = int(_native.load().cholmod_compute_units())
     assert cus > 0
     cases = [make_case(orc, n, k, sg, f32, 5100 + i) + (sg, f32)
              for i, (n, k, sg, f32) in enumerate(MIXED)]
-    single, stat1, _, _ = run_both(cases)
-    for plan in tune.candidates(cus) + [{"schedule": 0, "grid": 1, "order": 1, "poll": 1}]:
+    single_maps, _, _, _ = run_both(cases)
+    single_rot, _, _, _ = run_both(cases, rotations=True)
+    extra = [{"schedule": 0, "grid": 1, "order": 1, "poll": 1, "maps": 1},
+             {"schedule": 0, "grid": 0, "order": 0, "poll": 2, "maps": 0}]
+    for plan in tune.candidates(cus) + extra:
         print_case("batched-plan", **plan)
         Ls = [to_dev(L, f32) for L, _, _, f32 in cases]
         Vs = [to_dev(V, f32) for _, V, _, f32 in cases]
         stats = chm.update_batched(Ls, Vs, [c[2] for c in cases], plan=plan)
+        maps = plan["schedule"] == 0 and plan.get("maps", 1) == 1
+        single = single_maps if maps else single_rot
         for i, L in enumerate(Ls):
             assert stats[i][0] == 0, (plan, i, stats[i])
             assert np.array_equal(single[i], L.cpu().numpy().astype(np.float64)), (plan, i)

@@ -13,10 +13,12 @@ pytestmark = pytest.mark.gpu
 
 
 def incore(L, V, sigma):
-    """The device entry point on a GPU copy; returns (L_new on host, status, row, col)."""
+    """The device entry point on a GPU copy, every block by its rotations (as
+    the out-of-core form applies them); returns (L_new on host, status, row,
+    col)."""
     import paper_1011_1173_amd as chm
     Ld, Vd = L.cuda(), V.cuda()
-    st, row, col = chm.update_async(Ld, Vd, sigma).status()
+    st, row, col = chm.update_async(Ld, Vd, sigma, rotations=True).status()
     return Ld.cpu(), st, row, col
 
 

@@ -211,17 +211,49 @@ def test_sync_entry_point_and_python_errors(orc):
     (1500, 2, -1), (2049, 16, -1),
 ])
 def test_chain_schedule_equals_row_schedule_bitwise(orc, n, k, sigma):
-    """The default fast schedule (the owner schedule: 64-row blocks, each run
-    as a systolic chain by the workgroup owning its columns, which has applied
-    the earlier blocks to them) and the per-row fast schedule run the same
-    Compute/Apply arithmetic in the same per-element order: their results must
-    be identical bit for bit (k <= 16: one pass in both)."""
+    """The owner schedule with every block applied by its rotations (64-row
+    blocks, each run as a systolic chain by the workgroup owning its columns,
+    which has applied the earlier blocks to them) and the per-row fast
+    schedule run the same Compute/Apply arithmetic in the same per-element
+    order: their results must be identical bit for bit (k <= 16: one pass in
+    both).  The default, which applies blocks far from an owner by their
+    block maps, agrees with both to the FP64 tolerance and with the oracle."""
     print_case("schedules", n=n, k=k, sigma=sigma)
     L, V = inputs_for(orc, n, k, 3000 + n + k, sigma)
-    a, sa, _, _ = run_gpu(L, V, sigma)
+    a, sa, _, _ = run_gpu(L, V, sigma, rotations=True)
     b, sb, _, _ = run_gpu(L, V, sigma, blocked=True)
     assert sa == 0 and sb == 0
     assert np.array_equal(a, b), "max |diff| = %g" % np.abs(a - b).max()
+    c, sc, _, _ = run_gpu(L, V, sigma)
+    assert sc == 0
+    if n <= 192:  # no block is three or more blocks before an owner: no map is used
+        assert np.array_equal(a, c)
+    ref, st, _ = orc.modify(L, V, sigma)
+    assert st == 0
+    assert rel_diff(c, ref) <= RESID_TOL and rel_diff(c, a) <= RESID_TOL
+
+
+@pytest.mark.parametrize("sigma,scale", [(-1, 0.9), (-1, 0.5), (1, 3.0)])
+def test_block_maps_with_large_rotations(orc, sigma, scale):
+    """A rank-1 modification whose row-150 rotation is large: for a downdate
+    by 0.9 times row 150 of L, 1/c = 2.3 there, so the map of block 2 has
+    entries beyond the bound for maps and every owner applies that block by
+    its rotations; for 0.5 (1/c = 1.15) and for an update the map is used.
+    Either way the result is the oracle's within the FP64 tolerance (scaled by
+    the downdate's conditioning, 1 / (1 - scale^2))."""
+    n = 1000
+    print_case("maps-large", sigma=sigma, scale=scale)
+    L, _ = problem(n, 1, seed=3300)
+    V = np.zeros((n, 1))
+    V[:, 0] = scale * L[150, :n]
+    a, sa, _, _ = run_gpu(L, V, sigma)
+    assert sa == 0
+    ref, st, _ = orc.modify(L, V, sigma)
+    assert st == 0
+    cond = 1.0 / (1.0 - scale * scale) if sigma < 0 else 1.0
+    assert rel_diff(a, ref) <= RESID_TOL * cond
+    b, sb, _, _ = run_gpu(L, V, sigma, rotations=True)
+    assert sb == 0 and rel_diff(a, b) <= RESID_TOL * cond
 
 
 @pytest.mark.parametrize("n,k,sigma", [(300, 33, 1), (200, 21, -1), (130, 47, 1)])

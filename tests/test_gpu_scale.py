@@ -36,13 +36,20 @@ def test_more_workgroups_than_compute_units(n, k, sigma):
     L = inputs.spd_factor(n, seed=61, device="cuda")
     V = inputs.update_vectors(n, k, seed=61, device="cuda")
     a = L.clone()
-    st, _, _ = chm.update_async(a, V, sigma).status()
+    st, _, _ = chm.update_async(a, V, sigma, rotations=True).status()
     assert st == 0
     b = L.clone()
     st, _, _ = chm.update_async(b, V, sigma, blocked=True).status()
     assert st == 0
     assert torch.equal(a, b), "max |diff| = %g" % float((a - b).abs().max())
     assert probe_residual(a, L, V, sigma) <= 1e-12
+    # the default (far blocks by their maps) agrees to the FP64 tolerance
+    c = L.clone()
+    st, _, _ = chm.update_async(c, V, sigma).status()
+    assert st == 0
+    assert float(torch.linalg.norm(c - a) / torch.linalg.norm(a)) <= 1e-12
+    assert probe_residual(c, L, V, sigma) <= 1e-12
+    a = c
     # and back: the matching downdate restores L to rounding
     st, _, _ = chm.update_async(a, V, -sigma).status()
     assert st == 0
