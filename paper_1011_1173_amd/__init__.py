@@ -409,6 +409,14 @@ class Server:
             self._h = None
             self._pending.clear()
 
+    def __del__(self):
+        # a server left open would keep its worker thread (which makes HIP
+        # calls) running into interpreter shutdown
+        try:
+            self.close()
+        except Exception:
+            pass
+
     def __enter__(self):
         return self
 

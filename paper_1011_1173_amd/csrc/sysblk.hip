@@ -430,9 +430,15 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kMapPairs = 76;                // (row tile, k-step) operands stored
 constexpr int kMapElems = kMapPairs * 64;    // doubles per map
 constexpr int kLdM = kBR + kKP;              // row stride of the map being built
-constexpr int kMapLanes = kLdM / 4 * 16;     // apply lanes of the build: 320
 constexpr double kMapBound = 2.0;
 constexpr int kNear = 3;                     // blocks before an owner's own applied by rotations
+constexpr int kMinUses = 3;                  // a map is built only for this many owners or more
+
+// Blocks [0, map_blocks(nb)) of a factor of nb blocks get maps: block b's
+// map serves the owners of blocks b + kNear + 1 .. nb - 1.
+__host__ __device__ constexpr int64_t map_blocks(int64_t nb) {
+  return nb - kNear - kMinUses > 0 ? nb - kNear - kMinUses : 0;
+}
 enum : int32_t { kMapNone = 0, kMapOk = 1, kMapRot = 2 };
 
 __host__ __device__ constexpr int map_base(int I) {
@@ -459,23 +465,41 @@ template <int SG, int KCF>
 __device__ __forceinline__ void map_build(SbLds& sh, int kc, double* __restrict__ Mg,
                                           int32_t* __restrict__ state) {
   const int tid = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   double* const tile = &sh.Lh[0][0];  // 64 x 80
   double* const vm = &sh.Hb[0][0][0];  // 16 x 80: V's rows of the result
   for (int idx = tid; idx < kBR * kLdM; idx += kThreads)
     tile[idx] = (idx / kLdM == idx % kLdM) ? 1.0 : 0.0;
   __syncthreads();
-  if (tid < kMapLanes) {
+  // Waves 0-3 take the unit columns of the block's rows, 16 each; wave 7
+  // (on the SIMD of wave 3, which has the least work) those of V.  Unit
+  // column q < 64 stays zero, and V with it, until row q: wave c starts at
+  // sub-step 16 c, where the lanes of h > 0 hold rows before its columns
+  // (zero), so it skips the sub-steps that would only carry zeros.
+  if (wv < 4 || wv == 7) {
+    const int lt = wv < 4 ? tid : tid - 448 + kOwnThreads;
+    const int s0 = wv < 4 ? 16 * wv : 0;
+    const int kcc = KCF ? KCF : kc;
+    const int h = (lt & 15) >> 1, c0 = own_col(lt, 0);
+    const int hf = (kcc - 1) >> 1;
+    const bool first = (kcc & 1) != 0;
     double w[kOwnCols];
 #pragma unroll
     for (int k = 0; k < 2; ++k)
 #pragma unroll
       for (int u = 0; u < 2; ++u)
-        w[2 * k + u] = own_col(tid, u) - kBR == own_rot(tid, k) ? 1.0 : 0.0;
-    apply2x2<SG, double, KCF, kLdM>(sh, tile, kc, tid, w);
+        w[2 * k + u] = own_col(lt, u) - kBR == own_rot(lt, k) ? 1.0 : 0.0;
+    double xin[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) xin[u] = h == 0 ? tile[s0 * kLdM + c0 + u] : 0.0;
+    const RotRec* rp = &sh.R[kPad - h][2 * h];
+    RotRec qa[2] = {rp[s0 * kKP], rp[s0 * kKP + 1]};
+    int s = s0;
+    sub2x2_run<SG, double, kLdM>(tile, rp, s, kBR + hf, h, c0, hf, first, w, xin, qa);
 #pragma unroll
     for (int k = 0; k < 2; ++k)
 #pragma unroll
-      for (int u = 0; u < 2; ++u) vm[own_rot(tid, k) * kLdM + own_col(tid, u)] = w[2 * k + u];
+      for (int u = 0; u < 2; ++u) vm[own_rot(lt, k) * kLdM + own_col(lt, u)] = w[2 * k + u];
   }
   __syncthreads();
   bool bad = false;
@@ -1344,10 +1368,10 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
   const int64_t ldw = F.k;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int64_t nb = (F.n + kBR - 1) / kBR;
-  // blocks [0, nfar) by their maps (the owners of blocks up to j - kNear - 1
-  // find them built: each is built right after its chain), the rest by
+  // blocks [0, nfar) by their maps (blocks before j - kNear, whose maps are
+  // built right after their chains, if they have maps at all), the rest by
   // their rotations
-  const int nfar = F.maps ? imax(0, j - kNear) : 0;
+  const int nfar = F.maps ? imax(0, imin(j - kNear, (int)map_blocks(nb))) : 0;
   double* const maps = F.maps ? F.maps + (int64_t)pass * nb * kMapElems : nullptr;
   int32_t* const mstate = F.maps ? F.mstate + (int64_t)pass * nb : nullptr;
   double* const vbuf = &sh.Hb[0][0][0];  // 16 x 64: V between the two layouts
@@ -1489,7 +1513,7 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
               (unsigned long long)info_key(pj * F.k + m0, kCodeTimeout));
   __syncthreads();
   // the block's map, for the owners of blocks j + kNear + 1 and later
-  if (F.maps && j + kNear + 1 < nb) {
+  if (F.maps && j < map_blocks(nb)) {
     map_build<SG, KCF>(sh, kc, maps + (int64_t)j * kMapElems, mstate + j);
     __syncthreads();
   }
