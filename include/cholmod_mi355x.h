@@ -49,12 +49,13 @@
  *     its workgroups wait for rotation records and block maps that earlier
  *     workgroups publish; such a wait is bounded, and a launch whose wait ran
  *     out (not expected while the GPU runs the launch) reports
- *     CHOLMOD_ERR_HIP.  A workgroup applies a block three or more blocks
+ *     CHOLMOD_ERR_HIP.  A workgroup applies a block four or more blocks
  *     before its own by the block's map -- the block's rotations multiplied
  *     out into one 80 x 80 matrix, applied on the FP64 matrix cores -- which
  *     equals the rotation-by-rotation Apply up to rounding (maps whose
  *     entries exceed 2 in magnitude, as in a downdate close to
- *     indefiniteness, are not used).
+ *     indefiniteness, are not used; the last six blocks of a factor have no
+ *     maps).
  *   CHOLMOD_FLAG_ROTATIONS: the fast mode with every block applied by its
  *     rotations, which is bit for bit the per-row fast schedule's result.
  */

@@ -24,10 +24,10 @@ hipError_t run_blocked(hipStream_t st, double* L, int64_t n, int64_t ldl, double
                        double sg, Coef* T, int64_t* info, int64_t* stop, bool exact);
 hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
                       double sg, Coef* T, int64_t* info, int64_t* stop, int32_t* tickets,
-                      double* maps, int32_t* mstate);
+                      double* maps);
 hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, float* W, int64_t k,
                           double sg, void* T, int64_t* info, int64_t* stop, int32_t* tickets,
-                          double* maps, int32_t* mstate);
+                          double* maps);
 hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
                             const BatchEntry* d_ent, const BatchStep* steps, int64_t nsteps);
 hipError_t run_sysblk_batch_prepare(hipStream_t st, const BatchFactor* d_fac, int64_t count);
@@ -56,9 +56,8 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 //                    schedule's work counter)
 //   M                (with maps) the fast schedule's block maps: 76 x 64
 //                    doubles per block and 16-column pass
-//   S                (with maps) one int32 state per block map
 struct WsLayout {
-  size_t ctrl = 0, w = 0, t = 0, f = 0, m = 0, s = 0, total = 0;
+  size_t ctrl = 0, w = 0, t = 0, f = 0, m = 0, total = 0;
   int64_t nflags = 0, nmaps = 0;
 };
 
@@ -84,8 +83,7 @@ bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out, bool maps = true
   L.nflags = (k + 15) / 16;
   L.m = L.f + align_up((size_t)L.nflags * sizeof(int32_t));
   L.nmaps = maps ? L.nflags * ((n + 63) / 64) : 0;
-  L.s = L.m + (size_t)L.nmaps * kMapBytes;
-  L.total = L.s + align_up((size_t)L.nmaps * sizeof(int32_t));
+  L.total = L.m + (size_t)L.nmaps * kMapBytes;
   *out = L;
   return true;
 }
@@ -149,8 +147,7 @@ int enqueue_f64(double* L, const double* V, int64_t n, int64_t k, int64_t ldl, i
   } else {
     const bool maps = (flags & CHOLMOD_FLAG_ROTATIONS) == 0 && lay.nmaps > 0;
     e = run_sysblk(st, L, n, ldl, W, k, sg, T, d_info, stop_row, F,
-                   maps ? (double*)(base + lay.m) : nullptr,
-                   maps ? (int32_t*)(base + lay.s) : nullptr);
+                   maps ? (double*)(base + lay.m) : nullptr);
   }
   return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
 }
@@ -181,8 +178,7 @@ int enqueue_f32s(float* L, const float* V, int64_t n, int64_t k, int64_t ldl, in
   if (n == 0 || k == 0) return CHOLMOD_OK;
   const bool maps = (flags & CHOLMOD_FLAG_ROTATIONS) == 0 && lay.nmaps > 0;
   hipError_t e = run_sysblk_f32(st, L, n, ldl, W, k, (double)sigma, T, d_info, stop_row, F,
-                                maps ? (double*)(base + lay.m) : nullptr,
-                                maps ? (int32_t*)(base + lay.s) : nullptr);
+                                maps ? (double*)(base + lay.m) : nullptr);
   return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
 }
 
@@ -281,7 +277,7 @@ struct BatchPlan {
   std::vector<BatchStep> steps;
   std::vector<QItem> items;
   size_t off_ent = 0, off_items = 0, off_ticket = 0, off_left = 0, table_bytes = 0, total = 0;
-  std::vector<size_t> off_ctrl, off_w, off_t, off_m, off_s;  // off_m, off_s: 0 = no maps
+  std::vector<size_t> off_ctrl, off_w, off_t, off_m;  // off_m: 0 = no maps
 };
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -328,7 +324,6 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P,
   P->off_w.resize(count);
   P->off_t.resize(count);
   P->off_m.assign(count, 0);
-  P->off_s.assign(count, 0);
   for (int64_t f = 0; f < count; ++f) {
     const cholmod_desc& d = descs[f];
     WsLayout lay;
@@ -336,10 +331,7 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P,
     P->off_ctrl[f] = off + lay.ctrl;
     P->off_w[f] = off + lay.w;
     P->off_t[f] = off + lay.t;
-    if (lay.nmaps > 0) {
-      P->off_m[f] = off + lay.m;
-      P->off_s[f] = off + lay.s;
-    }
+    if (lay.nmaps > 0) P->off_m[f] = off + lay.m;
     off += lay.total;
   }
   P->total = off;
@@ -358,7 +350,6 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P,
     F.left = queued ? (int32_t*)(ws + P->off_left) + f : nullptr;
     F.done = nullptr;  // set by a caller that wants per-factor completion
     F.maps = P->off_m[f] ? (void*)(ws + P->off_m[f]) : nullptr;
-    F.mstate = P->off_s[f] ? (int32_t*)(ws + P->off_s[f]) : nullptr;
     F.n = d.n;
     F.k = d.k;
     F.ldl = d.ldl;

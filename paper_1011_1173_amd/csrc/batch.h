@@ -19,8 +19,7 @@ struct BatchFactor {
   int64_t* done;   // queued form, or null: where the last item to finish
                    // writes the factor's info word (host-mapped memory)
   void* maps;      // queued form, or null (every block by its rotations): the
-                   // block maps, kMapElems doubles per block and pass
-  int32_t* mstate; // their states, one per block and pass
+                   // block maps, 76 x 64 doubles per block and pass
   int64_t n, k, ldl;
   int32_t sigma, dtype;
 };

@@ -439,7 +439,18 @@ constexpr int kMinUses = 3;                  // a map is built only for this man
 __host__ __device__ constexpr int64_t map_blocks(int64_t nb) {
   return nb - kNear - kMinUses > 0 ? nb - kNear - kMinUses : 0;
 }
-enum : int32_t { kMapNone = 0, kMapOk = 1, kMapRot = 2 };
+
+// 8-byte words of a factor's map region: one map per block and pass.
+__host__ __device__ constexpr int64_t map_words(int64_t n, int64_t k) {
+  return ((k + kKP - 1) / kKP) * ((n + kBR - 1) / kBR) * kMapElems;
+}
+enum : int32_t { kMapOk = 1, kMapRot = 2 };
+// Map entries as published: a map region starts filled with kMapEmpty (a
+// signalling NaN, which no arithmetic result is) and an unusable map is
+// published as kMapRotate in every entry, so that, as with the rotation
+// records, the data is its own ready flag and needs no fence or flag store.
+constexpr uint64_t kMapEmpty = 0x7FF4A5A5A5A5A5A5ull;
+constexpr uint64_t kMapRotate = 0x7FF4A5A5A5A5A5A6ull;
 
 __host__ __device__ constexpr int map_base(int I) {
   return I == 0 ? 0 : I == 1 ? 8 : I == 2 ? 20 : I == 3 ? 36 : 56;
@@ -462,8 +473,7 @@ __device__ __forceinline__ void map_entry(int e, int l, int& row, int& col) {
 // device-scope stores, and the map's state (usable or not) is stored after a
 // device-scope fence.  Uses sh.Lh and sh.Hb; all threads of the workgroup.
 template <int SG, int KCF>
-__device__ __forceinline__ void map_build(SbLds& sh, int kc, double* __restrict__ Mg,
-                                          int32_t* __restrict__ state) {
+__device__ __forceinline__ void map_build(SbLds& sh, int kc, double* __restrict__ Mg) {
   const int tid = threadIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   double* const tile = &sh.Lh[0][0];  // 64 x 80
@@ -502,62 +512,61 @@ __device__ __forceinline__ void map_build(SbLds& sh, int kc, double* __restrict_
       for (int u = 0; u < 2; ++u) vm[own_rot(lt, k) * kLdM + own_col(lt, u)] = w[2 * k + u];
   }
   __syncthreads();
+  constexpr int kPer = (kMapElems + kThreads - 1) / kThreads;  // 10
+  uint64_t v[kPer];
   bool bad = false;
-  for (int idx = tid; idx < kMapElems; idx += kThreads) {
-    int row, col;
-    map_entry(idx >> 6, idx & 63, row, col);
-    const double v = row < kBR ? tile[row * kLdM + col] : vm[(row - kBR) * kLdM + col];
-    bad |= !(__builtin_fabs(v) <= kMapBound);
-    __hip_atomic_store(reinterpret_cast<uint64_t*>(Mg + idx), __builtin_bit_cast(uint64_t, v),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int idx = tid + q * kThreads;
+    double x = 0.0;
+    if (idx < kMapElems) {
+      int row, col;
+      map_entry(idx >> 6, idx & 63, row, col);
+      x = row < kBR ? tile[row * kLdM + col] : vm[(row - kBR) * kLdM + col];
+    }
+    bad |= !(__builtin_fabs(x) <= kMapBound);
+    v[q] = __builtin_bit_cast(uint64_t, x);
   }
-  __threadfence();  // every thread's map stores, device-wide, before the state
-  const int anybad = __syncthreads_or(bad);
-  if (tid == 0)
-    __hip_atomic_store(state, anybad ? (int32_t)kMapRot : (int32_t)kMapOk, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+  const bool rotate = __syncthreads_or(bad) != 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int idx = tid + q * kThreads;
+    if (idx < kMapElems)
+      __hip_atomic_store(reinterpret_cast<uint64_t*>(Mg + idx), rotate ? kMapRotate : v[q],
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
-// Wait for a map's state (one thread): kMapOk or kMapRot; a wait that runs
-// past the deadline sets sh.tmo and reports kMapRot.
-__device__ __forceinline__ int map_wait(SbLds& sh, const int32_t* state, int64_t deadline) {
+// Stage map Mb into LDS at dst: wave q of the four staging waves copies
+// doubles [q * 1216, q * 1216 + 1216) once none of them is kMapEmpty any
+// more (it polls, sleeping between polls; past the deadline it sets sh.tmo
+// and gives up).  Returns kMapOk, or kMapRot for a map published as
+// unusable (then nothing is copied); every staging wave finds the same.
+constexpr int kMapPerWave = kMapElems / 4;  // 1216 = 19 x 64
+__device__ __forceinline__ int map_stage(SbLds& sh, const double* Mb, double* dst,
+                                         int64_t deadline, int q, int lane) {
+  constexpr int kN = kMapPerWave / 64;
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(Mb + q * kMapPerWave) + lane;
+  uint64_t v[kN];
   for (;;) {
-    const int v = __hip_atomic_load(const_cast<int32_t*>(state), __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
-    if (v != kMapNone) return v;
+    bool full = true;
+#pragma unroll
+    for (int i = 0; i < kN; ++i) {
+      v[i] = __hip_atomic_load(const_cast<uint64_t*>(src + i * 64), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      full &= v[i] != kMapEmpty;
+    }
+    if (__all(full)) break;
     if (wall_clock64() > deadline) {
       sh.tmo = 1;
       return kMapRot;
     }
     __builtin_amdgcn_s_sleep(20);
   }
-}
-
-__device__ __forceinline__ double map_ld(const double* p) {
-  return __builtin_bit_cast(double, __hip_atomic_load(reinterpret_cast<uint64_t*>(
-                                                          const_cast<double*>(p)),
-                                                      __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT));
-}
-
-// Stage map Mb into LDS at dst (wave q of the four staging waves copies
-// doubles [q * 1216, q * 1216 + 1216)), after waiting for the map's state,
-// which every staging wave reads for itself; returns the state (the map is
-// copied only if it is usable).
-constexpr int kMapPerWave = kMapElems / 4;  // 1216 = 19 x 64
-__device__ __forceinline__ int map_stage(SbLds& sh, const double* Mb, const int32_t* state,
-                                         double* dst, int64_t deadline, int q, int lane) {
-  int st = 0;
-  if (lane == 0) st = map_wait(sh, state, deadline);
-  st = __builtin_amdgcn_readfirstlane(st);
-  if (st == kMapOk) {
-    double v[kMapPerWave / 64];
+  if (__builtin_amdgcn_readfirstlane((int)(v[0] == kMapRotate))) return kMapRot;
 #pragma unroll
-    for (int i = 0; i < kMapPerWave / 64; ++i) v[i] = map_ld(Mb + q * kMapPerWave + i * 64 + lane);
-#pragma unroll
-    for (int i = 0; i < kMapPerWave / 64; ++i) dst[q * kMapPerWave + i * 64 + lane] = v[i];
-  }
-  return st;
+  for (int i = 0; i < kN; ++i) dst[q * kMapPerWave + i * 64 + lane] = __builtin_bit_cast(double, v[i]);
+  return kMapOk;
 }
 
 // B operands of the owner's tile (rows [pb, pb + 64), columns 16 ct ..
@@ -1315,15 +1324,14 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
 
 // One factor as the owner kernels see it.  Pass p (columns 16p .. of V)
 // keeps its records at T + p * n * 16 and the maps of its blocks at
-// maps + p * nb * kMapElems, their states at mstate + p * nb (nb blocks);
-// maps == nullptr: every block is applied by its rotations.
+// maps + p * nb * kMapElems (nb blocks); maps == nullptr: every block is
+// applied by its rotations.
 template <typename ST>
 struct OwnF {
   ST* L;
   const ST* W;  // private copy of V, row stride k
   GRec<ST>* T;
   double* maps;
-  int32_t* mstate;
   int64_t* info;
   int64_t* stop;
   int64_t n, k, ldl;
@@ -1373,7 +1381,6 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
   // their rotations
   const int nfar = F.maps ? imax(0, imin(j - kNear, (int)map_blocks(nb))) : 0;
   double* const maps = F.maps ? F.maps + (int64_t)pass * nb * kMapElems : nullptr;
-  int32_t* const mstate = F.maps ? F.mstate + (int64_t)pass * nb : nullptr;
   double* const vbuf = &sh.Hb[0][0][0];  // 16 x 64: V between the two layouts
   // every global input of the pass is issued before anything is staged: V
   // of the block's columns and the first tile
@@ -1415,7 +1422,7 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
     auto mbuf = [&](int b) -> double* { return (b & 1) ? &sh.R[0][0].c : &sh.Lh[0][0]; };
     double bx[16];
     if (wv >= 4) {
-      const int st = map_stage(sh, maps, mstate, mbuf(0), deadline, wv - 4, lane);
+      const int st = map_stage(sh, maps, mbuf(0), deadline, wv - 4, lane);
       if (wv == 4 && lane == 0) sh.mfl[0] = st;
     } else {
       map_tile_load<ST>(bx, F.L, F.ldl, 0, pj, bbc, wv, lane);
@@ -1429,8 +1436,8 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
           map_apply<ST>(mbuf(b), bx, F.L, F.ldl, pb, pj, bbc, wv, lane, vx);
           if (more) map_tile_load<ST>(bx, F.L, F.ldl, pb + kBR, pj, bbc, wv, lane);
         } else if (more) {
-          const int st = map_stage(sh, maps + (int64_t)(b + 1) * kMapElems, mstate + b + 1,
-                                   mbuf(b + 1), deadline, wv - 4, lane);
+          const int st = map_stage(sh, maps + (int64_t)(b + 1) * kMapElems, mbuf(b + 1),
+                                   deadline, wv - 4, lane);
           if (wv == 4 && lane == 0) sh.mfl[(b + 1) & 1] = st;
         }
         __syncthreads();
@@ -1463,8 +1470,8 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
           for (int r = 0; r < 4; ++r) vx[r] = vbuf[(4 * r + (lane >> 4)) * kBR + 16 * wv + (lane & 15)];
           if (more) map_tile_load<ST>(bx, F.L, F.ldl, pb + kBR, pj, bbc, wv, lane);
         } else if (more) {
-          const int st = map_stage(sh, maps + (int64_t)(b + 1) * kMapElems, mstate + b + 1,
-                                   mbuf(b + 1), deadline, wv - 4, lane);
+          const int st = map_stage(sh, maps + (int64_t)(b + 1) * kMapElems, mbuf(b + 1),
+                                   deadline, wv - 4, lane);
           if (wv == 4 && lane == 0) sh.mfl[(b + 1) & 1] = st;
         }
         __syncthreads();
@@ -1514,7 +1521,7 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
   __syncthreads();
   // the block's map, for the owners of blocks j + kNear + 1 and later
   if (F.maps && j < map_blocks(nb)) {
-    map_build<SG, KCF>(sh, kc, maps + (int64_t)j * kMapElems, mstate + j);
+    map_build<SG, KCF>(sh, kc, maps + (int64_t)j * kMapElems);
     __syncthreads();
   }
 }
@@ -1571,7 +1578,6 @@ __device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int
     OwnF<double> F;
     F.L = (double*)B.L;
     F.maps = (double*)B.maps;
-    F.mstate = B.mstate;
     F.W = (const double*)B.W;
     F.T = (GRec<double>*)B.T;
     F.info = B.info;
@@ -1585,7 +1591,6 @@ __device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int
     OwnF<float> F;
     F.L = (float*)B.L;
     F.maps = (double*)B.maps;
-    F.mstate = B.mstate;
     F.W = (const float*)B.W;
     F.T = (GRec<float>*)B.T;
     F.info = B.info;
@@ -1667,21 +1672,23 @@ __global__ void k_prepare_qbatch(const BatchFactor* __restrict__ fac,
   }
   // no block map is built yet
   if (F.maps != nullptr) {
-    const int64_t nstate = passes * ((F.n + kBR - 1) / kBR);
-    for (int64_t i = i0; i < nstate; i += stride) F.mstate[i] = kMapNone;
+    uint64_t* __restrict__ m = (uint64_t*)F.maps;
+    const int64_t mwords = map_words(F.n, F.k);
+    for (int64_t i = i0; i < mwords; i += stride) m[i] = kMapEmpty;
   }
 }
 
 // Records of one pass start out empty.
 template <typename ST>
 __global__ void k_owner_clear(GRec<ST>* __restrict__ T, int64_t words,
-                              int32_t* __restrict__ mstate, int64_t nstate) {
+                              double* __restrict__ maps, int64_t mwords) {
   using U = typename RecBits<ST>::U;
   U* __restrict__ p = reinterpret_cast<U*>(T);
+  uint64_t* __restrict__ m = reinterpret_cast<uint64_t*>(maps);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = i0; i < words; i += stride) p[i] = RecBits<ST>::kEmpty;
-  for (int64_t i = i0; i < nstate; i += stride) mstate[i] = kMapNone;
+  for (int64_t i = i0; i < mwords; i += stride) m[i] = kMapEmpty;
 }
 
 // ------------------------------------------------------- latency probes
@@ -1853,22 +1860,21 @@ int owner_grid_limit() {
 // out empty.
 template <typename ST>
 hipError_t run_sysblk_t(hipStream_t st, ST* L, int64_t n, int64_t ldl, ST* W, int64_t k, int sg,
-                        void* Tws, int64_t* info, int64_t* stop, int32_t* tickets, double* maps,
-                        int32_t* mstate) {
+                        void* Tws, int64_t* info, int64_t* stop, int32_t* tickets,
+                        double* maps) {
   GRec<ST>* R = reinterpret_cast<GRec<ST>*>(Tws);
   const int64_t nb = (n + kBR - 1) / kBR;
   const int64_t passes = (k + kKP - 1) / kKP;
   const int64_t words = n * kKP * 4 * passes;
-  const int64_t nstate = maps ? passes * nb : 0;
-  const int64_t cblocks = (words + 255) / 256;
+  const int64_t mwords = maps ? map_words(n, k) : 0;
+  const int64_t cblocks = (words + mwords + 255) / 256;
   const unsigned cgrid = (unsigned)(cblocks < 4096 ? cblocks : 4096);
-  hipLaunchKernelGGL(k_owner_clear<ST>, dim3(cgrid), dim3(256), 0, st, R, words, mstate, nstate);
+  hipLaunchKernelGGL(k_owner_clear<ST>, dim3(cgrid), dim3(256), 0, st, R, words, maps, mwords);
   OwnF<ST> F;
   F.L = L;
   F.W = W;
   F.T = R;
   F.maps = maps;
-  F.mstate = mstate;
   F.info = info;
   F.stop = stop;
   F.n = n;
@@ -1933,9 +1939,8 @@ hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t co
 // tickets holds one zeroed int32 per pass.
 hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
                       double sg, Coef* T, int64_t* info, int64_t* stop, int32_t* tickets,
-                      double* maps, int32_t* mstate) {
-  return run_sysblk_t<double>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets, maps,
-                              mstate);
+                      double* maps) {
+  return run_sysblk_t<double>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets, maps);
 }
 
 // The same schedule with L, V and the records stored in FP32: the rows of a
@@ -1944,9 +1949,8 @@ hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double*
 // FP64 by block maps.
 hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, float* W, int64_t k,
                           double sg, void* T, int64_t* info, int64_t* stop, int32_t* tickets,
-                          double* maps, int32_t* mstate) {
-  return run_sysblk_t<float>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets, maps,
-                             mstate);
+                          double* maps) {
+  return run_sysblk_t<float>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets, maps);
 }
 
 // Latency probes (see k_probe_chain, k_probe_handoff): out[0] ns per chain

@@ -226,7 +226,7 @@ def test_chain_schedule_equals_row_schedule_bitwise(orc, n, k, sigma):
     assert np.array_equal(a, b), "max |diff| = %g" % np.abs(a - b).max()
     c, sc, _, _ = run_gpu(L, V, sigma)
     assert sc == 0
-    if n <= 192:  # no block is three or more blocks before an owner: no map is used
+    if n <= 384:  # a factor of 6 blocks or fewer has no block maps
         assert np.array_equal(a, c)
     ref, st, _ = orc.modify(L, V, sigma)
     assert st == 0
