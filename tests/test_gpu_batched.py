@@ -104,12 +104,12 @@ def test_batched_uneven_pool(orc):
 
 
 def test_every_tuned_plan_equals_single_bitwise(orc):
-    """Every launch plan the autotuner may pick (stepped or queued; queued
-    with fewer workgroups, factor-major order, other poll levels, with or
-    without block maps) leaves each factor of the mixed batch bit for bit
-    where the single-factor path does: the default single-factor path for a
-    queued plan with maps, the single-factor path with every block by its
-    rotations otherwise."""
+    """Every launch plan the autotuner may pick (queued with block maps: fewer
+    workgroups, factor-major order, other poll levels) and the plans outside
+    its set (stepped, queued without maps) leave each factor of the mixed
+    batch bit for bit where the single-factor path does: the default
+    single-factor path for a queued plan with maps, the single-factor path
+    with every block by its rotations otherwise."""
     import paper_1011_1173_amd as chm
     from paper_1011_1173_amd import _native, tune
     cus = int(_native.load().cholmod_compute_units())
@@ -119,7 +119,8 @@ def test_every_tuned_plan_equals_single_bitwise(orc):
     single_maps, _, _, _ = run_both(cases)
     single_rot, _, _, _ = run_both(cases, rotations=True)
     extra = [{"schedule": 0, "grid": 1, "order": 1, "poll": 1, "maps": 1},
-             {"schedule": 0, "grid": 0, "order": 0, "poll": 2, "maps": 0}]
+             {"schedule": 0, "grid": 0, "order": 0, "poll": 2, "maps": 0},
+             {"schedule": 1, "grid": 0, "order": 0, "poll": 2, "maps": 0}]
     for plan in tune.candidates(cus) + extra:
         print_case("batched-plan", **plan)
         Ls = [to_dev(L, f32) for L, _, _, f32 in cases]
