@@ -58,8 +58,6 @@
 // form's launches for later blocks and passes skip the rows at or after
 // it; the owner schedule simply carries on (every later value is
 // unspecified) and the first failure stays the reported one.
-#include <type_traits>
-
 #include "rotations.h"
 #include "batch.h"
 
@@ -542,14 +540,24 @@ __device__ __forceinline__ void map_build(SbLds& sh, int kc, double* __restrict_
 // more (it polls, sleeping between polls; past the deadline it sets sh.tmo
 // and gives up).  Returns kMapOk, or kMapRot for a map published as
 // unusable (then nothing is copied); every staging wave finds the same.
+// The first read goes through the caches: an entry is written once per
+// launch, so a cached copy is either still kMapEmpty or final, and the
+// owners on one XCD then share one fetch of the map; only a read that still
+// finds empty entries polls with device-scope loads.
 constexpr int kMapPerWave = kMapElems / 4;  // 1216 = 19 x 64
 __device__ __forceinline__ int map_stage(SbLds& sh, const double* Mb, double* dst,
                                          int64_t deadline, int q, int lane) {
   constexpr int kN = kMapPerWave / 64;
   const uint64_t* src = reinterpret_cast<const uint64_t*>(Mb + q * kMapPerWave) + lane;
   uint64_t v[kN];
-  for (;;) {
-    bool full = true;
+  bool full = true;
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    v[i] = src[i * 64];
+    full &= v[i] != kMapEmpty;
+  }
+  while (!__all(full)) {
+    full = true;
 #pragma unroll
     for (int i = 0; i < kN; ++i) {
       v[i] = __hip_atomic_load(const_cast<uint64_t*>(src + i * 64), __ATOMIC_RELAXED,
@@ -596,6 +604,34 @@ __device__ __forceinline__ void map_rows(const double* Mb, int lane, const doubl
                                                acc, 0, 0, 0);
 }
 
+// Row tiles I and J (map_lk(I) <= map_lk(J)) together, their products
+// interleaved so that each accumulation chain's latency hides behind the
+// other's.
+template <int I, int J>
+__device__ __forceinline__ void map_rows2(const double* Mb, int lane, const double (&bx)[16],
+                                          const double (&vx)[4], v4d& ai, v4d& aj) {
+  constexpr int ni = map_lk(I), nj = map_lk(J);
+  static_assert(ni <= nj, "row tile order");
+#pragma unroll
+  for (int K = 0; K < ni; ++K) {
+    ai = __builtin_amdgcn_mfma_f64_16x16x4f64(Mb[(map_base(I) + K) * 64 + lane], bx[K], ai, 0,
+                                              0, 0);
+    aj = __builtin_amdgcn_mfma_f64_16x16x4f64(Mb[(map_base(J) + K) * 64 + lane], bx[K], aj, 0,
+                                              0, 0);
+  }
+#pragma unroll
+  for (int K = ni; K < nj; ++K)
+    aj = __builtin_amdgcn_mfma_f64_16x16x4f64(Mb[(map_base(J) + K) * 64 + lane], bx[K], aj, 0,
+                                              0, 0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ai = __builtin_amdgcn_mfma_f64_16x16x4f64(Mb[(map_base(I) + ni + q) * 64 + lane], vx[q], ai,
+                                              0, 0, 0);
+    aj = __builtin_amdgcn_mfma_f64_16x16x4f64(Mb[(map_base(J) + nj + q) * 64 + lane], vx[q], aj,
+                                              0, 0, 0);
+  }
+}
+
 // Apply the map staged in LDS at Mb to the wave's 16 columns of the owner's
 // tile, whose B operands are in bx (map_tile_load), one wave; the result
 // rows go to L, and vx (V of those columns: lane l, element r is row
@@ -606,28 +642,32 @@ __device__ __forceinline__ void map_apply(const double* Mb, const double (&bx)[1
                                           int64_t pj, int bbc, int ct, int lane,
                                           double (&vx)[4]) {
   const int g = lane >> 4, cl = 16 * ct + (lane & 15);
-  // one row tile after the other (V's last, vx is an input of all five),
-  // each stored at once, so that few accumulators and operands are live
-  // (the scheduling barriers keep the compiler from hoisting every operand
-  // load of the block)
-  auto rows = [&](auto I_, v4d& acc) {
-    constexpr int I = decltype(I_)::value;
-    acc = (v4d){0.0, 0.0, 0.0, 0.0};
-    map_rows<I>(Mb, lane, bx, vx, acc);
-    if (I < 4 && cl < bbc) {
+  // two row tiles at a time (V's last: vx is an input of all five), each
+  // stored at once, so that few accumulators and operands are live (the
+  // scheduling barriers keep the compiler from hoisting every operand load
+  // of the block)
+  auto store = [&](int I, const v4d& acc) {
+    if (cl < bbc) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) L[(pb + 16 * I + 4 * r + g) * ldl + pj + cl] = (ST)acc[r];
     }
-    __builtin_amdgcn_sched_barrier(0);
   };
-  v4d a, b;
-  rows(std::integral_constant<int, 0>{}, a);
-  rows(std::integral_constant<int, 1>{}, b);
-  rows(std::integral_constant<int, 2>{}, a);
-  rows(std::integral_constant<int, 3>{}, b);
-  rows(std::integral_constant<int, 4>{}, a);
+  const v4d z = {0.0, 0.0, 0.0, 0.0};
+  v4d a = z, b = z;
+  map_rows<0>(Mb, lane, bx, vx, a);
+  store(0, a);
+  __builtin_amdgcn_sched_barrier(0);
+  a = z;
+  map_rows2<1, 2>(Mb, lane, bx, vx, a, b);
+  store(1, a);
+  store(2, b);
+  __builtin_amdgcn_sched_barrier(0);
+  a = z;
+  b = z;
+  map_rows2<3, 4>(Mb, lane, bx, vx, a, b);
+  store(3, a);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) vx[r] = a[r];
+  for (int r = 0; r < 4; ++r) vx[r] = b[r];
 }
 
 // ------------------------------------------------------------------ chain
