@@ -220,19 +220,43 @@ class PendingBatch:
 
 
 def _descs(Ls, Vs, sigmas):
-    if not (len(Ls) == len(Vs) == len(sigmas)):
+    """Descriptor array of a batch.  The checks of _factor_args, inlined with
+    as few tensor queries as possible (a batch has hundreds of factors and
+    this runs on the host before every batched call); any factor that fails
+    them goes through _factor_args for its error message."""
+    count = len(Ls)
+    if not (count == len(Vs) == len(sigmas)):
         raise ArgumentError("Ls, Vs and sigmas must have the same length")
-    arr = (_native.Desc * max(1, len(Ls)))()
-    ks, dev = [], None
-    for i, (L, V, sg) in enumerate(zip(Ls, Vs, sigmas)):
-        n, k, ldl, V = _factor_args(L, V)
+    arr = (_native.Desc * max(1, count))()
+    ks = [0] * count
+    dev = None
+    f64, f32, Desc = torch.float64, torch.float32, _native.Desc
+    for i in range(count):
+        L, V = Ls[i], Vs[i]
+        try:
+            dt = L.dtype
+            d = L.device
+            shp, st = L.shape, L.stride()
+            if V.dim() == 1:
+                V = V.view(-1, 1)
+            vs = V.shape
+            n = shp[0]
+            ldl = st[0] if n > 1 else max(1, shp[1])
+            ok = ((dt is f64 or dt is f32) and V.dtype is dt and d.type == "cuda"
+                  and V.device == d and len(shp) == 2 and st[1] == 1 and shp[1] >= n
+                  and ldl >= max(1, n) and len(vs) == 2 and vs[0] == n and V.is_contiguous())
+        except (AttributeError, TypeError, IndexError, RuntimeError):
+            ok = False
+        if not ok:
+            _factor_args(L, V)  # raises ArgumentError with the reason
+            raise ArgumentError("factor %d: unsupported L or V" % i)
         if dev is None:
-            dev = L.device
-        elif L.device != dev:
+            dev = d
+        elif d != dev:
             raise ArgumentError("all factors of a batch must be on one GPU")
-        arr[i] = _native.Desc(L.data_ptr(), V.data_ptr(), n, k, ldl, int(sg),
-                              F32S if L.dtype == torch.float32 else F64)
-        ks.append(k)
+        arr[i] = Desc(L.data_ptr(), V.data_ptr(), n, vs[1], ldl, int(sigmas[i]),
+                      F32S if dt is f32 else F64)
+        ks[i] = vs[1]
     return arr, ks, dev
 
 

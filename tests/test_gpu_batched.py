@@ -131,3 +131,30 @@ def test_every_tuned_plan_equals_single_bitwise(orc):
         for i, L in enumerate(Ls):
             assert stats[i][0] == 0, (plan, i, stats[i])
             assert np.array_equal(single[i], L.cpu().numpy().astype(np.float64)), (plan, i)
+
+
+def test_tuner_writes_a_cache_the_library_loads(tmp_path):
+    """The autotuner on one small bucket: it checks every candidate against
+    the default plan bit for bit, writes the fastest to a plan cache, and the
+    cache goes into the library's plan table."""
+    import ctypes
+    from paper_1011_1173_amd import _native, tune
+    print_case("tuner")
+    out = tmp_path / "plans.json"
+    data = tune.tune(str(out), dtypes=("f64",), n_buckets=(0,), k_buckets=(0,), reps=1)
+    assert len(data["entries"]) == 1
+    e = data["entries"][0]
+    assert (e["dtype"], e["n_bucket"], e["k_bucket"]) == (0, 0, 0)
+    assert e["plan"]["schedule"] == 0 and e["plan"]["maps"] == 1
+    assert e["ms"] > 0 and e["default_ms"] >= e["ms"]
+    lib = _native.load()
+    keep = _native.Plan()
+    assert lib.cholmod_get_plan(_native.F64, 0, 0, ctypes.byref(keep)) == _native.OK
+    try:
+        assert tune.load_plans(str(out)) == 1
+        got = _native.Plan()
+        assert lib.cholmod_get_plan(_native.F64, 0, 0, ctypes.byref(got)) == _native.OK
+        assert (got.schedule, got.grid, got.order, got.poll, got.maps) == tuple(
+            e["plan"][f] for f in ("schedule", "grid", "order", "poll", "maps"))
+    finally:
+        lib.cholmod_set_plan(_native.F64, 0, 0, ctypes.byref(keep))
