@@ -1558,12 +1558,18 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
   if (tid == 0 && sh.tmo)
     atomicMin((unsigned long long*)F.info,
               (unsigned long long)info_key(pj * F.k + m0, kCodeTimeout));
-  __syncthreads();
   // the block's map, for the owners of blocks j + kNear + 1 and later
   if (F.maps && j < map_blocks(nb)) {
-    map_build<SG, KCF>(sh, kc, maps + (int64_t)j * kMapElems);
+    // the build's pipeline runs past the block's rows, where it must find
+    // identity records: the chain's lanes that ran past the block left the
+    // records of rows they computed for nothing there (of rotations that are
+    // the identity only up to the near-zero V values they read)
+    for (int idx = tid; idx < kKP * kKP; idx += kThreads)
+      sh.R[kPad + kBR + (idx >> 4)][idx & 15] = identity_rec();
     __syncthreads();
+    map_build<SG, KCF>(sh, kc, maps + (int64_t)j * kMapElems);
   }
+  __syncthreads();
 }
 
 // Every pass of the owner of block j.  The passes of one block run in order;
