@@ -297,7 +297,7 @@ def batched(args):
 
 
 def sweep(args):
-    """Single-factor sweep: n in {10000, 20000, 40000}, k in {1, 16, 64},
+    """Single-factor sweep: n in {10000, 20000, 40000}, k in {1, 16, 17, 32, 64},
     FP64 and FP32 storage.  Per configuration: one untimed update/downdate
     pair, then 3 timed pairs (HIP events around each modification on a
     dedicated stream).  Reports ms per modification (median), updates/s,
@@ -315,7 +315,7 @@ def sweep(args):
         L64 = inputs.spd_factor(n, seed=3, device="cuda")
         for dt, es in ((torch.float64, 8), (torch.float32, 4)):
             L0 = L64.to(dt)
-            for k in (1, 16, 64):
+            for k in (1, 16, 17, 32, 64):
                 V = inputs.update_vectors(n, k, seed=3, device="cuda").to(dt)
                 L = L0.clone()
                 torch.cuda.synchronize()  # L and V were written on the default stream
@@ -351,7 +351,7 @@ def sweep(args):
            "value": None, "unit": "see rows", "n_gpus": 1, "higher_is_better": False,
            "dtype": "f64+f32s", "data": "synthetic",
            "config": {"block_apply": "rotations" if args.rotations else "maps for far blocks",
-                      "workload": "sweep: n in {1e4, 2e4, 4e4} x k in {1, 16, 64} x "
+                      "workload": "sweep: n in {1e4, 2e4, 4e4} x k in {1, 16, 17, 32, 64} x "
                                   "{FP64, FP32 storage}, update then matching downdate"},
            "rows": rows}
     print(json.dumps(out))

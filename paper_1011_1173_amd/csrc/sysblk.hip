@@ -127,8 +127,8 @@ struct SbLds {
   int tmo;                  // owner schedule: a wait ran out of time
   int cnt[2][4];            // owner schedule: rows of each 16-row window of the applied
                             // block staged, by round parity
-  int mfl[2];               // owner schedule: state of the applied block's map, by block
-                            // parity
+  int mst[2][4];            // owner schedule: what each staging wave found of the map in
+                            // buffer 0 / 1 (kMapOk, kMapRot, kMapWait)
 };
 
 // Row shift by D lanes within each 16-lane row (DPP row_shr:D); the first D
@@ -442,7 +442,7 @@ __host__ __device__ constexpr int64_t map_blocks(int64_t nb) {
 __host__ __device__ constexpr int64_t map_words(int64_t n, int64_t k) {
   return ((k + kKP - 1) / kKP) * ((n + kBR - 1) / kBR) * kMapElems;
 }
-enum : int32_t { kMapOk = 1, kMapRot = 2 };
+enum : int32_t { kMapOk = 1, kMapRot = 2, kMapWait = 3 };
 // Map entries as published: a map region starts filled with kMapEmpty (a
 // signalling NaN, which no arithmetic result is) and an unusable map is
 // published as kMapRotate in every entry, so that, as with the rotation
@@ -570,6 +570,35 @@ __device__ __forceinline__ int map_stage(SbLds& sh, const double* Mb, double* ds
       return kMapRot;
     }
     __builtin_amdgcn_s_sleep(20);
+  }
+  if (__builtin_amdgcn_readfirstlane((int)(v[0] == kMapRotate))) return kMapRot;
+#pragma unroll
+  for (int i = 0; i < kN; ++i) dst[q * kMapPerWave + i * 64 + lane] = __builtin_bit_cast(double, v[i]);
+  return kMapOk;
+}
+
+// map_stage without waiting: kMapWait (nothing copied) if an entry of wave
+// q's quarter is still empty after a second, device-scope read.
+__device__ __forceinline__ int map_try_stage(SbLds& sh, const double* Mb, double* dst, int q,
+                                             int lane) {
+  constexpr int kN = kMapPerWave / 64;
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(Mb + q * kMapPerWave) + lane;
+  uint64_t v[kN];
+  bool full = true;
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    v[i] = src[i * 64];
+    full &= v[i] != kMapEmpty;
+  }
+  if (!__all(full)) {
+    full = true;
+#pragma unroll
+    for (int i = 0; i < kN; ++i) {
+      v[i] = __hip_atomic_load(const_cast<uint64_t*>(src + i * 64), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      full &= v[i] != kMapEmpty;
+    }
+    if (!__all(full)) return kMapWait;
   }
   if (__builtin_amdgcn_readfirstlane((int)(v[0] == kMapRotate))) return kMapRot;
 #pragma unroll
@@ -1369,12 +1398,13 @@ __device__ __forceinline__ void owner_apply(SbLds& sh, int kc_, int64_t pb,
 template <typename ST>
 struct OwnF {
   ST* L;
-  const ST* W;  // private copy of V, row stride k
+  ST* W;  // private copy of V, row stride k
   GRec<ST>* T;
   double* maps;
   int64_t* info;
   int64_t* stop;
   int64_t n, k, ldl;
+  int fuse;  // pass pairs share their far blocks' tile traffic (binary64 storage)
 };
 
 // V of apply lane tid's columns from rows m of buf[m * 64 + c] (the 16 x 64
@@ -1406,32 +1436,44 @@ __device__ __forceinline__ void w_to_lds(const ST (&w)[kOwnCols], double* buf, i
 // triangle goes to L, else back to sh.Lb for the next pass.
 template <int SG, typename ST, int KCF>
 __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, int bbc,
-                                           int pass, bool last, int64_t deadline, int poll) {
+                                           int pass, bool last, int64_t deadline, int poll,
+                                           int& nfz) {
   const int tid = threadIdx.x;
   const int64_t m0 = (int64_t)pass * kKP;
   const int kc = KCF ? KCF : (int)(F.k - m0 < kKP ? F.k - m0 : kKP);
   const int64_t pj = (int64_t)j * kBR;
   GRec<ST>* const T = F.T + (int64_t)pass * F.n * kKP;
-  const ST* const W = F.W + m0;
+  ST* const W = F.W + m0;
   const int64_t ldw = F.k;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int64_t nb = (F.n + kBR - 1) / kBR;
   // blocks [0, nfar) by their maps (blocks before j - kNear, whose maps are
   // built right after their chains, if they have maps at all), the rest by
-  // their rotations
+  // their rotations.  Passes run in pairs: pass p (even) also applies the
+  // maps of pass p + 1 (its "fused" blocks) while it has the tile at hand,
+  // for blocks whose pass p + 1 map is published already, and leaves V of
+  // pass p + 1 in the private copy; pass p + 1 then starts at block nfz.
   const int nfar = F.maps ? imax(0, imin(j - kNear, (int)map_blocks(nb))) : 0;
+  const int b0 = (pass & 1) ? nfz : 0;
+  const bool far = nfar > b0;
+  const bool fuse = F.fuse && far && (pass & 1) == 0 && m0 + kKP < F.k;
+  const int kc1 = fuse ? (int)(F.k - m0 - kKP < kKP ? F.k - m0 - kKP : kKP) : 0;
+  if ((pass & 1) == 0) nfz = 0;
   double* const maps = F.maps ? F.maps + (int64_t)pass * nb * kMapElems : nullptr;
+  double* const maps1 = fuse ? maps + nb * kMapElems : nullptr;
   double* const vbuf = &sh.Hb[0][0][0];  // 16 x 64: V between the two layouts
   // every global input of the pass is issued before anything is staged: V
   // of the block's columns and the first tile
   ST w[kOwnCols];
-  double vx[4];  // map layout (waves 0-3): row 4 r + lane / 16 of V, column 16 wv + lane % 16
-  if (nfar > 0) {
+  double vx[4];   // map layout (waves 0-3): row 4 r + lane / 16 of V, column 16 wv + lane % 16
+  double vx1[4];  // ... of pass p + 1, while fusing
+  if (far) {
     const int cl = 16 * wv + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int m = 4 * r + (lane >> 4);
       vx[r] = (wv < 4 && cl < bbc && m < kc) ? (double)W[(pj + cl) * ldw + m] : 0.0;
+      vx1[r] = (wv < 4 && cl < bbc && m < kc1) ? (double)W[(pj + cl) * ldw + kKP + m] : 0.0;
     }
   } else {
 #pragma unroll
@@ -1443,47 +1485,106 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
       }
   }
   TileRegs<ST> tr;
-  if (nfar == 0 && j > 0) tile_issue_a(tr, F.L, F.ldl, 0, pj, bbc);
+  if (!far && nfar < j) tile_issue_a(tr, F.L, F.ldl, (int64_t)nfar * kBR, pj, bbc);
   // identity records everywhere: the pad rows keep them, each block's rows
   // are overwritten as they arrive (after the far blocks, whose maps are
   // staged where the records go)
-  if (nfar == 0)
+  if (!far)
     for (int idx = tid; idx < kRRows * kKP; idx += kThreads) sh.R[idx >> 4][idx & 15] = identity_rec();
   __syncthreads();
   chain_setup_tri(sh, bbc);  // needs only the triangle: done before the applies
-  if (nfar > 0) {
-    // Far blocks: waves 0-3 multiply block b's map (staged in LDS buffer
-    // b & 1) into their columns while waves 4-7 stage the map of block b+1
-    // into the other buffer; each wave 0-3 loads its B operands of block
-    // b+1 during block b's products.  A map that is not usable makes the
-    // workgroup apply that block by its rotations.
-    // map buffer of block b: the apply tile's region for even b, the
-    // records' for odd b
-    auto mbuf = [&](int b) -> double* { return (b & 1) ? &sh.R[0][0].c : &sh.Lh[0][0]; };
+  if (far) {
+    // Far blocks: waves 0-3 multiply a map (staged in LDS buffer ib) into
+    // their columns while waves 4-7 stage the next map into the other
+    // buffer; each wave 0-3 loads its B operands of the next tile during the
+    // products.  The maps go in the order (b, pass p), then, while fusing,
+    // (b, pass p + 1) on the same tile (stored after the first product,
+    // read again from the cache).  A pass p map that is not usable makes
+    // the workgroup apply that block by its rotations; a pass p + 1 map
+    // that is not there yet (or not usable) ends the fusing.
+    // map buffer ib: the apply tile's region (0) or the records' (1)
+    auto mbuf = [&](int ib) -> double* { return ib ? &sh.R[0][0].c : &sh.Lh[0][0]; };
+    // the staging waves' findings on the map of buffer ib, combined
+    auto state = [&](int ib) {
+      int ok = 1, rot = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int v = sh.mst[ib][q];
+        ok &= v == kMapOk;
+        rot |= v == kMapRot;
+      }
+      return ok ? kMapOk : rot ? kMapRot : kMapWait;
+    };
     double bx[16];
+    int b = b0, sp = 0, ib = 0;  // the current map: block b, pass p + sp, in buffer ib
+    bool fusing = fuse;
     if (wv >= 4) {
-      const int st = map_stage(sh, maps, mbuf(0), deadline, wv - 4, lane);
-      if (wv == 4 && lane == 0) sh.mfl[0] = st;
+      sh.mst[0][wv - 4] = map_stage(sh, maps + (int64_t)b * kMapElems, mbuf(0), deadline, wv - 4,
+                                    lane);
     } else {
-      map_tile_load<ST>(bx, F.L, F.ldl, 0, pj, bbc, wv, lane);
+      map_tile_load<ST>(bx, F.L, F.ldl, (int64_t)b * kBR, pj, bbc, wv, lane);
     }
     __syncthreads();
-    for (int b = 0; b < nfar; ++b) {
+    while (b < nfar) {
       const int64_t pb = (int64_t)b * kBR;
-      const bool more = b + 1 < nfar;
-      if (sh.mfl[b & 1] == kMapOk) {
+      const int st = state(ib);
+      if (sp == 1 && st != kMapOk) {
+        // block b's pass p + 1 map is not there: pass p + 1 resumes here
+        // (vx holds pass p + 1's V since the swap before this map)
+        fusing = false;
+        nfz = b;
+        sp = 0;
         if (wv < 4) {
-          map_apply<ST>(mbuf(b), bx, F.L, F.ldl, pb, pj, bbc, wv, lane, vx);
-          if (more) map_tile_load<ST>(bx, F.L, F.ldl, pb + kBR, pj, bbc, wv, lane);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double t = vx[r];
+            vx[r] = vx1[r];
+            vx1[r] = t;
+          }
+        }
+        if (++b >= nfar) break;
+        // block b + 1's pass p map into the other buffer (the one just
+        // applied), so that nobody rewrites the state being read
+        if (wv >= 4) {
+          sh.mst[ib ^ 1][wv - 4] = map_stage(sh, maps + (int64_t)b * kMapElems, mbuf(ib ^ 1),
+                                             deadline, wv - 4, lane);
+        } else {
+          map_tile_load<ST>(bx, F.L, F.ldl, (int64_t)b * kBR, pj, bbc, wv, lane);
+        }
+        __syncthreads();
+        ib ^= 1;
+        continue;
+      }
+      if (st != kMapOk && fusing) {
+        fusing = false;  // block b goes by its rotations: pass p + 1 resumes here
+        nfz = b;
+      }
+      // the map after this one
+      const int bn = (fusing && sp == 0) ? b : b + 1, sn = (fusing && sp == 0) ? 1 : 0;
+      const bool more = bn < nfar;
+      if (st == kMapOk) {
+        if (wv < 4) {
+          // one call site for both passes of a pair (the product is large):
+          // vx holds the V of the map's pass, vx1 the other's
+          map_apply<ST>(mbuf(ib), bx, F.L, F.ldl, pb, pj, bbc, wv, lane, vx);
+          if (sp != sn) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const double t = vx[r];
+              vx[r] = vx1[r];
+              vx1[r] = t;
+            }
+          }
+          if (more) map_tile_load<ST>(bx, F.L, F.ldl, (int64_t)bn * kBR, pj, bbc, wv, lane);
         } else if (more) {
-          const int st = map_stage(sh, maps + (int64_t)(b + 1) * kMapElems, mbuf(b + 1),
-                                   deadline, wv - 4, lane);
-          if (wv == 4 && lane == 0) sh.mfl[(b + 1) & 1] = st;
+          const double* src = (sn ? maps1 : maps) + (int64_t)bn * kMapElems;
+          sh.mst[ib ^ 1][wv - 4] = sn ? map_try_stage(sh, src, mbuf(ib ^ 1), wv - 4, lane)
+                                      : map_stage(sh, src, mbuf(ib ^ 1), deadline, wv - 4, lane);
         }
         __syncthreads();
       } else {
-        // by the block's rotations (the map buffers are free: block b+1's
-        // map is staged afterwards); V to the rotation layout and back
+        // by the block's rotations (the map buffers are free: the next map
+        // is staged afterwards); V to the rotation layout and back
         if (wv < 4) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) vbuf[(4 * r + (lane >> 4)) * kBR + 16 * wv + (lane & 15)] = vx[r];
@@ -1508,13 +1609,25 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
         if (wv < 4) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) vx[r] = vbuf[(4 * r + (lane >> 4)) * kBR + 16 * wv + (lane & 15)];
-          if (more) map_tile_load<ST>(bx, F.L, F.ldl, pb + kBR, pj, bbc, wv, lane);
+          if (more) map_tile_load<ST>(bx, F.L, F.ldl, (int64_t)bn * kBR, pj, bbc, wv, lane);
         } else if (more) {
-          const int st = map_stage(sh, maps + (int64_t)(b + 1) * kMapElems, mbuf(b + 1),
-                                   deadline, wv - 4, lane);
-          if (wv == 4 && lane == 0) sh.mfl[(b + 1) & 1] = st;
+          sh.mst[ib ^ 1][wv - 4] = map_stage(sh, maps + (int64_t)bn * kMapElems, mbuf(ib ^ 1),
+                                             deadline, wv - 4, lane);
         }
         __syncthreads();
+      }
+      b = bn;
+      sp = sn;
+      ib ^= 1;
+    }
+    if (fusing) nfz = nfar;  // every far block's pass p + 1 map is applied
+    if (fuse && wv < 4) {
+      // V of pass p + 1 after blocks [0, nfz), for pass p + 1
+      const int cl = 16 * wv + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = 4 * r + (lane >> 4);
+        if (cl < bbc && m < kc1) W[(pj + cl) * ldw + kKP + m] = (ST)vx1[r];
       }
     }
     // V to the rotation layout for the rest; the records get their identity
@@ -1590,12 +1703,13 @@ __device__ __forceinline__ void owner_item(SbLds& sh, const OwnF<ST>& F, int j, 
     sh.Lb[i][c] = (i < bbc && c < bbc && c >= i) ? (double)F.L[(pj + i) * F.ldl + pj + c] : 0.0;
   }
   const int passes = (int)((F.k + kKP - 1) / kKP);
+  int nfz = 0;  // far blocks of the odd pass applied by the even pass before it
   for (int p = 0; p < passes; ++p) {
     const bool last = p + 1 == passes;
     if (SPEC16 && F.k - (int64_t)p * kKP >= kKP)
-      owner_pass<SG, ST, kKP>(sh, F, j, bbc, p, last, deadline, poll);
+      owner_pass<SG, ST, kKP>(sh, F, j, bbc, p, last, deadline, poll, nfz);
     else
-      owner_pass<SG, ST, 0>(sh, F, j, bbc, p, last, deadline, poll);
+      owner_pass<SG, ST, 0>(sh, F, j, bbc, p, last, deadline, poll, nfz);
   }
 }
 
@@ -1624,26 +1738,28 @@ __device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int
     OwnF<double> F;
     F.L = (double*)B.L;
     F.maps = (double*)B.maps;
-    F.W = (const double*)B.W;
+    F.W = (double*)B.W;
     F.T = (GRec<double>*)B.T;
     F.info = B.info;
     F.stop = B.stop;
     F.n = B.n;
     F.k = B.k;
     F.ldl = B.ldl;
+    F.fuse = 0;  // measured: no gain for queued batches
     if (B.sigma > 0) owner_item<1, double, true>(sh, F, j, poll);
     else owner_item<-1, double, true>(sh, F, j, poll);
   } else {
     OwnF<float> F;
     F.L = (float*)B.L;
     F.maps = (double*)B.maps;
-    F.W = (const float*)B.W;
+    F.W = (float*)B.W;
     F.T = (GRec<float>*)B.T;
     F.info = B.info;
     F.stop = B.stop;
     F.n = B.n;
     F.k = B.k;
     F.ldl = B.ldl;
+    F.fuse = 0;
     if (B.sigma > 0) owner_item<1, float, true>(sh, F, j, poll);
     else owner_item<-1, float, true>(sh, F, j, poll);
   }
@@ -1927,6 +2043,11 @@ hipError_t run_sysblk_t(hipStream_t st, ST* L, int64_t n, int64_t ldl, ST* W, in
   F.k = k;
   F.ldl = ldl;
   const int lim = owner_grid_limit();
+  // pass pairs share the far blocks' tiles where owners start late enough
+  // to find the later pass's maps published (more blocks than compute
+  // units; measured: no gain below), and only with binary64 storage, where
+  // V of the later pass is kept exactly in the private copy
+  F.fuse = (sizeof(ST) == sizeof(double) && nb > (int64_t)lim) ? 1 : 0;
   const unsigned grid = (unsigned)(nb < lim ? nb : lim);
   auto kern = sg > 0 ? k_sb_queue<1, ST> : k_sb_queue<-1, ST>;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, F, (int)nb, tickets);

@@ -15,7 +15,7 @@ for this input recipe, which leaves the normalised maximum near 1e-15 --
 ELEM_TOL = 1e-13 keeps two orders of magnitude of margin and still catches a
 localised error far below what the Frobenius norm would show.
 
-Cases: n = 5000 (the headline shape) with k in {1, 16, 64} and sigma = +-1;
+Cases: n = 5000 (the headline shape) with k in {1, 16, 17, 33, 64} and sigma = +-1;
 n = 17000, k = 16 (266 blocks of 64 rows: more blocks than compute units,
 the late-owner regime), the whole factor; and the exact evaluation mode at
 n = 5000, k = 16 bit for bit.  The downdate cases downdate the oracle's
@@ -100,7 +100,7 @@ def check(out, ref, Lin, V, sigma, resid=True):
         assert r <= RESID_TOL, r
 
 
-@pytest.mark.parametrize("k", [1, 16, 64])
+@pytest.mark.parametrize("k", [1, 16, 17, 33, 64])
 @pytest.mark.parametrize("sigma", [1, -1])
 def test_fast_path_elementwise_headline_shape(orc, k, sigma):
     n = 5000
