@@ -27,7 +27,7 @@ hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double*
                       double* maps);
 hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, float* W, int64_t k,
                           double sg, void* T, int64_t* info, int64_t* stop, int32_t* tickets,
-                          double* maps);
+                          double* maps, double* carry);
 hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t count,
                             const BatchEntry* d_ent, const BatchStep* steps, int64_t nsteps);
 hipError_t run_sysblk_batch_prepare(hipStream_t st, const BatchFactor* d_fac, int64_t count);
@@ -56,8 +56,11 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 //                    schedule's work counter)
 //   M                (with maps) the fast schedule's block maps: 76 x 64
 //                    doubles per block and 16-column pass
+//   C                (binary32 storage with maps, one factor) V of the odd
+//                    pass of each pass pair, n x 16 doubles per pair, that
+//                    the even pass leaves for it
 struct WsLayout {
-  size_t ctrl = 0, w = 0, t = 0, f = 0, m = 0, total = 0;
+  size_t ctrl = 0, w = 0, t = 0, f = 0, m = 0, c = 0, total = 0;
   int64_t nflags = 0, nmaps = 0;
 };
 
@@ -65,7 +68,8 @@ constexpr size_t kMapBytes = 76 * 64 * sizeof(double);
 
 bool mul_ok(int64_t a, int64_t b, int64_t lim) { return a == 0 || b <= lim / a; }
 
-bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out, bool maps = true) {
+bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out, bool maps = true,
+                bool carry = true) {
   if (n < 0 || k < 0) return false;
   if (dtype != CHOLMOD_F64 && dtype != CHOLMOD_F32S) return false;
   const int64_t lim = INT64_MAX / 64;
@@ -84,6 +88,10 @@ bool layout_for(int64_t n, int64_t k, int dtype, WsLayout* out, bool maps = true
   L.m = L.f + align_up((size_t)L.nflags * sizeof(int32_t));
   L.nmaps = maps ? L.nflags * ((n + 63) / 64) : 0;
   L.total = L.m + (size_t)L.nmaps * kMapBytes;
+  if (carry && dtype == CHOLMOD_F32S && L.nmaps > 0 && L.nflags >= 2) {
+    L.c = L.total;
+    L.total = L.c + align_up((size_t)(L.nflags / 2) * (size_t)n * 16 * sizeof(double));
+  }
   *out = L;
   return true;
 }
@@ -178,7 +186,8 @@ int enqueue_f32s(float* L, const float* V, int64_t n, int64_t k, int64_t ldl, in
   if (n == 0 || k == 0) return CHOLMOD_OK;
   const bool maps = (flags & CHOLMOD_FLAG_ROTATIONS) == 0 && lay.nmaps > 0;
   hipError_t e = run_sysblk_f32(st, L, n, ldl, W, k, (double)sigma, T, d_info, stop_row, F,
-                                maps ? (double*)(base + lay.m) : nullptr);
+                                maps ? (double*)(base + lay.m) : nullptr,
+                                maps && lay.c ? (double*)(base + lay.c) : nullptr);
   return e == hipSuccess ? CHOLMOD_OK : CHOLMOD_ERR_HIP;
 }
 
@@ -327,7 +336,7 @@ int plan_batch(const cholmod_desc* descs, int64_t count, char* ws, BatchPlan* P,
   for (int64_t f = 0; f < count; ++f) {
     const cholmod_desc& d = descs[f];
     WsLayout lay;
-    if (!layout_for(d.n, d.k, d.dtype, &lay, maps)) return CHOLMOD_ERR_ARG;
+    if (!layout_for(d.n, d.k, d.dtype, &lay, maps, false)) return CHOLMOD_ERR_ARG;
     P->off_ctrl[f] = off + lay.ctrl;
     P->off_w[f] = off + lay.w;
     P->off_t[f] = off + lay.t;

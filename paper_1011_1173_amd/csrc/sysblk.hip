@@ -1404,7 +1404,8 @@ struct OwnF {
   int64_t* info;
   int64_t* stop;
   int64_t n, k, ldl;
-  int fuse;  // pass pairs share their far blocks' tile traffic (binary64 storage)
+  int fuse;    // pass pairs share their far blocks' tiles
+  double* vc;  // binary32 storage: V of the odd pass of each pair, n x 16 per pair
 };
 
 // V of apply lane tid's columns from rows m of buf[m * 64 + c] (the 16 x 64
@@ -1454,11 +1455,17 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
   // for blocks whose pass p + 1 map is published already, and leaves V of
   // pass p + 1 in the private copy; pass p + 1 then starts at block nfz.
   const int nfar = F.maps ? imax(0, imin(j - kNear, (int)map_blocks(nb))) : 0;
-  const int b0 = (pass & 1) ? nfz : 0;
+  // nfz < 0: the even pass before did not pair (V of this pass is in W)
+  const bool carried = (pass & 1) && nfz >= 0;
+  const int b0 = carried ? nfz : 0;
   const bool far = nfar > b0;
   const bool fuse = F.fuse && far && (pass & 1) == 0 && m0 + kKP < F.k;
   const int kc1 = fuse ? (int)(F.k - m0 - kKP < kKP ? F.k - m0 - kKP : kKP) : 0;
-  if ((pass & 1) == 0) nfz = 0;
+  if ((pass & 1) == 0) nfz = fuse ? 0 : -1;
+  // where the odd pass of a pair finds its V: the private copy of V, or the
+  // carry area (binary32 storage, whose private copy would round it)
+  double* const vc = F.vc ? F.vc + (int64_t)(pass >> 1) * F.n * kKP : nullptr;
+  const bool from_vc = carried && vc != nullptr;
   double* const maps = F.maps ? F.maps + (int64_t)pass * nb * kMapElems : nullptr;
   double* const maps1 = fuse ? maps + nb * kMapElems : nullptr;
   double* const vbuf = &sh.Hb[0][0][0];  // 16 x 64: V between the two layouts
@@ -1472,7 +1479,8 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int m = 4 * r + (lane >> 4);
-      vx[r] = (wv < 4 && cl < bbc && m < kc) ? (double)W[(pj + cl) * ldw + m] : 0.0;
+      const bool ok = wv < 4 && cl < bbc && m < kc;
+      vx[r] = !ok ? 0.0 : from_vc ? vc[(pj + cl) * kKP + m] : (double)W[(pj + cl) * ldw + m];
       vx1[r] = (wv < 4 && cl < bbc && m < kc1) ? (double)W[(pj + cl) * ldw + kKP + m] : 0.0;
     }
   } else {
@@ -1481,7 +1489,8 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int c = own_col(tid, u), m = own_rot(tid, k);
-        w[2 * k + u] = (tid < kOwnThreads && c < bbc && m < kc) ? W[(pj + c) * ldw + m] : (ST)0;
+        const bool ok = tid < kOwnThreads && c < bbc && m < kc;
+        w[2 * k + u] = !ok ? (ST)0 : from_vc ? (ST)vc[(pj + c) * kKP + m] : W[(pj + c) * ldw + m];
       }
   }
   TileRegs<ST> tr;
@@ -1627,7 +1636,10 @@ __device__ __forceinline__ void owner_pass(SbLds& sh, const OwnF<ST>& F, int j, 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = 4 * r + (lane >> 4);
-        if (cl < bbc && m < kc1) W[(pj + cl) * ldw + kKP + m] = (ST)vx1[r];
+        if (cl < bbc && m < kc1) {
+          if (F.vc) F.vc[(int64_t)(pass >> 1) * F.n * kKP + (pj + cl) * kKP + m] = vx1[r];
+          else W[(pj + cl) * ldw + kKP + m] = (ST)vx1[r];
+        }
       }
     }
     // V to the rotation layout for the rest; the records get their identity
@@ -1703,7 +1715,7 @@ __device__ __forceinline__ void owner_item(SbLds& sh, const OwnF<ST>& F, int j, 
     sh.Lb[i][c] = (i < bbc && c < bbc && c >= i) ? (double)F.L[(pj + i) * F.ldl + pj + c] : 0.0;
   }
   const int passes = (int)((F.k + kKP - 1) / kKP);
-  int nfz = 0;  // far blocks of the odd pass applied by the even pass before it
+  int nfz = -1;  // far blocks of the odd pass applied by the even pass before it
   for (int p = 0; p < passes; ++p) {
     const bool last = p + 1 == passes;
     if (SPEC16 && F.k - (int64_t)p * kKP >= kKP)
@@ -1746,6 +1758,7 @@ __device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int
     F.k = B.k;
     F.ldl = B.ldl;
     F.fuse = 0;  // measured: no gain for queued batches
+    F.vc = nullptr;
     if (B.sigma > 0) owner_item<1, double, true>(sh, F, j, poll);
     else owner_item<-1, double, true>(sh, F, j, poll);
   } else {
@@ -1760,6 +1773,7 @@ __device__ __forceinline__ void qbatch_item(SbLds& sh, const BatchFactor& B, int
     F.k = B.k;
     F.ldl = B.ldl;
     F.fuse = 0;
+    F.vc = nullptr;
     if (B.sigma > 0) owner_item<1, float, true>(sh, F, j, poll);
     else owner_item<-1, float, true>(sh, F, j, poll);
   }
@@ -2023,7 +2037,7 @@ int owner_grid_limit() {
 template <typename ST>
 hipError_t run_sysblk_t(hipStream_t st, ST* L, int64_t n, int64_t ldl, ST* W, int64_t k, int sg,
                         void* Tws, int64_t* info, int64_t* stop, int32_t* tickets,
-                        double* maps) {
+                        double* maps, double* carry) {
   GRec<ST>* R = reinterpret_cast<GRec<ST>*>(Tws);
   const int64_t nb = (n + kBR - 1) / kBR;
   const int64_t passes = (k + kKP - 1) / kKP;
@@ -2045,9 +2059,10 @@ hipError_t run_sysblk_t(hipStream_t st, ST* L, int64_t n, int64_t ldl, ST* W, in
   const int lim = owner_grid_limit();
   // pass pairs share the far blocks' tiles where owners start late enough
   // to find the later pass's maps published (more blocks than compute
-  // units; measured: no gain below), and only with binary64 storage, where
-  // V of the later pass is kept exactly in the private copy
-  F.fuse = (sizeof(ST) == sizeof(double) && nb > (int64_t)lim) ? 1 : 0;
+  // units; measured: no gain below); V of the later pass is carried exactly,
+  // in the private copy of V (binary64 storage) or in `carry`
+  F.vc = sizeof(ST) == sizeof(double) ? nullptr : carry;
+  F.fuse = (maps && nb > (int64_t)lim && (sizeof(ST) == sizeof(double) || carry)) ? 1 : 0;
   const unsigned grid = (unsigned)(nb < lim ? nb : lim);
   auto kern = sg > 0 ? k_sb_queue<1, ST> : k_sb_queue<-1, ST>;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, F, (int)nb, tickets);
@@ -2107,7 +2122,8 @@ hipError_t run_sysblk_batch(hipStream_t st, const BatchFactor* d_fac, int64_t co
 hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double* W, int64_t k,
                       double sg, Coef* T, int64_t* info, int64_t* stop, int32_t* tickets,
                       double* maps) {
-  return run_sysblk_t<double>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets, maps);
+  return run_sysblk_t<double>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets, maps,
+                              nullptr);
 }
 
 // The same schedule with L, V and the records stored in FP32: the rows of a
@@ -2116,8 +2132,9 @@ hipError_t run_sysblk(hipStream_t st, double* L, int64_t n, int64_t ldl, double*
 // FP64 by block maps.
 hipError_t run_sysblk_f32(hipStream_t st, float* L, int64_t n, int64_t ldl, float* W, int64_t k,
                           double sg, void* T, int64_t* info, int64_t* stop, int32_t* tickets,
-                          double* maps) {
-  return run_sysblk_t<float>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets, maps);
+                          double* maps, double* carry) {
+  return run_sysblk_t<float>(st, L, n, ldl, W, k, sg > 0 ? 1 : -1, T, info, stop, tickets, maps,
+                             carry);
 }
 
 // Latency probes (see k_probe_chain, k_probe_handoff): out[0] ns per chain
