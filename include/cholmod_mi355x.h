@@ -111,7 +111,9 @@ int cholmod_decode_info(int64_t info, int64_t k, int64_t *row, int64_t *col);
  * n x k problem with the given storage type (CHOLMOD_F64 or CHOLMOD_F32S).
  * Returns 0 for invalid sizes.  The workspace holds the private copy of V,
  * the per-row rotation coefficients and the block maps (38,912 bytes per
- * 64-row block and 16-column pass); it needs 256-byte alignment.
+ * 64-row block and 16-column pass), and with CHOLMOD_F32S and k > 16 the
+ * binary64 values of V that a 16-column pass leaves for the next one (128
+ * bytes per row and pair of passes); it needs 256-byte alignment.
  */
 size_t cholmod_workspace_bytes(int64_t n, int64_t k, int dtype);
 
