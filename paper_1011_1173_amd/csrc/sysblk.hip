@@ -29,14 +29,15 @@
 // step t = i + m and passes the running radicand and 1/L_ii to lane m+1 with
 // a DPP row shift.  Column j of the block needs the rotations of all earlier
 // rows of the block before it becomes the diagonal:
-//   * rows r < j - 2 are applied by six helper waves, one lane per column
+//   * rows r < j - 2 are applied by seven helper waves, one lane per column
 //     j, in diagonal order: at step t a helper applies (r, m) with
 //     r + m = t - 1, whose record wave 0 wrote to LDS at step t - 1; the
-//     waves split the columns of V 3 + 3 + 3 + 3 + 2 + 2 and pass the partly
-//     rotated L_rj on through LDS.  The workgroup's 8 waves are spread over
-//     the 4 SIMDs round-robin, so wave 0 shares its SIMD only with wave 4,
-//     which idles, and the helpers pair up on the other three.  After each rotation the helper publishes V_j[m]
-//     (by step parity); the value after row j - 3 is the hand-off;
+//     waves split the columns of V 3 + 3 + 3 + 2 + 2 + 2 + 1 and pass the
+//     partly rotated L_rj on through LDS.  The workgroup's 8 waves are spread
+//     over the 4 SIMDs round-robin (waves w and w + 4 on SIMD w), so each of
+//     SIMDs 1-3 runs five columns and wave 0 shares SIMD 0 with the helper of
+//     one column.  After each rotation the helper publishes V_j[m] (by step
+//     parity); the value after row j - 3 is the hand-off;
 //   * lane m of wave 0 takes that hand-off and applies rows j - 2 and j - 1
 //     itself at step j - 1 + m (the partly rotated L_rj moving from lane m
 //     to lane m+1), so V_j is ready for Compute(j, m) at the next step.
@@ -118,7 +119,7 @@ struct SbLds {
     double Lh[kPad + kBR][kBR];  // helper results after the last rotation, rows -16..63
   };
   double Hb[kKP][2][kBR];   // V_j[m] after each helper rotation, by step parity
-  double X[5][2][kBR];      // helper h -> h+1, by step parity
+  double X[6][2][kBR];      // helper h -> h+1, by step parity
   Band Lc[kRRows];          // wave 0 results by row + 16
   Feed fd[kRRows];          // by row; rows >= bbc unused
   int64_t lim;              // first failing row known at launch
@@ -844,7 +845,7 @@ __device__ __forceinline__ void helper_step(SbLds& sh, double (&st)[kSt], int t,
       if (m == kc - 1) sh.Lh[imin(t - 1 - m + kPad, kPad + kBR - 1)][jj] = x;
     }
   }
-  if (H < 5) sh.X[H < 5 ? H : 0][t & 1][jj] = st[2 * CNT - 1];
+  if (H < 6) sh.X[H < 6 ? H : 0][t & 1][jj] = st[2 * CNT - 1];
   if (H == 0) st[2 * CNT] = sh.Lb[imin(t, kBR - 1)][jj];
 }
 
@@ -949,12 +950,48 @@ __device__ __forceinline__ void helper_steps(SbLds& sh, int nsteps, int lane, in
   }
 }
 
+template <typename ST>
+__device__ __forceinline__ void publish_rows(SbLds& sh, GRec<ST>* __restrict__ T, int64_t pc,
+                                             int r0, int kc, int lane);
+
+// The helper on wave 4 (column 15 of V), which also publishes the block's
+// records 4 rows at a time as they complete: after barrier u (u = t + 1
+// after step t) the rows up to u - kc are complete.  The records are read
+// from LDS right after that barrier and stored to T during the next step,
+// when the read has long completed, so that the step does not wait for it.
+template <int SG, typename ST, int KCF>
+__device__ __forceinline__ void helper_steps_pub(SbLds& sh, int nsteps, int lane, int kc,
+                                                 bool pub, GRec<ST>* __restrict__ T,
+                                                 int64_t pc) {
+  double st[kSt];
+  helper_init<15, 1>(sh, st, lane);
+  __syncthreads();
+  int q = 0;
+  bool have = false;
+  RotRec rec;
+  GRec<ST>* dst = T;
+  for (int t = 0; t < nsteps; ++t) {
+    helper_step<6, 15, 1, SG, KCF>(sh, st, t, lane, kc);
+    if (have) publish_record(dst, rec);
+    have = false;
+    __syncthreads();
+    if (pub && q < kBR / 4 && t + 1 == 4 * q + 3 + kc) {
+      const int r = 4 * q + (lane >> 4), m = lane & 15;
+      rec = sh.R[r + kPad][m];
+      dst = T + (pc + r) * kKP + m;
+      have = m < kc;
+      ++q;
+    }
+  }
+  if (have) publish_record(dst, rec);
+}
+
 // LDS set-up of a chain that needs only the block's triangle (staged in
 // sh.Lb): the helpers' transfer rows cleared, and each row's diagonal and
 // lane 0's inputs.
 __device__ __forceinline__ void chain_setup_tri(SbLds& sh, int bbc) {
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < 5 * kBR; idx += kThreads) sh.X[idx >> 6][1][idx & 63] = 0.0;
+  for (int idx = tid; idx < 6 * kBR; idx += kThreads) sh.X[idx >> 6][1][idx & 63] = 0.0;
   if (tid == 0) sh.fail = 0x7fffffff;
   if (tid < kRRows) {
     const int r = tid < kBR ? tid : kBR - 1;
@@ -1005,18 +1042,12 @@ __device__ __forceinline__ void chain_loops(SbLds& sh, int kc, int bbc, bool pub
   const int tid = threadIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int nsteps = bbc + kc - 1;
+  // columns of V per helper 3 3 3 2 2 2 1, so that each SIMD runs five
+  // (waves w and w + 4 share SIMD w; wave 0 runs the Computes)
   if (wv == 0) {
     chain_wave0<SG>(sh, lane, kc, nsteps);
   } else if (wv == 4) {
-    // shares its SIMD with wave 0: passes the same barriers and publishes
-    int q = 0;
-    for (int u = 0; u <= nsteps; ++u) {
-      __syncthreads();
-      if (pub && q < kBR / 4 && u == 4 * q + 3 + kc) {
-        publish_rows(sh, T, pc, 4 * q, kc, lane);
-        ++q;
-      }
-    }
+    helper_steps_pub<SG, ST, KCF>(sh, nsteps, lane, kc, pub, T, pc);
   } else if (wv == 1) {
     helper_steps<0, 0, 3, SG, KCF>(sh, nsteps, lane, kc);
   } else if (wv == 2) {
@@ -1024,11 +1055,11 @@ __device__ __forceinline__ void chain_loops(SbLds& sh, int kc, int bbc, bool pub
   } else if (wv == 3) {
     helper_steps<2, 6, 3, SG, KCF>(sh, nsteps, lane, kc);
   } else if (wv == 5) {
-    helper_steps<3, 9, 3, SG, KCF>(sh, nsteps, lane, kc);
+    helper_steps<3, 9, 2, SG, KCF>(sh, nsteps, lane, kc);
   } else if (wv == 6) {
-    helper_steps<4, 12, 2, SG, KCF>(sh, nsteps, lane, kc);
+    helper_steps<4, 11, 2, SG, KCF>(sh, nsteps, lane, kc);
   } else {
-    helper_steps<5, 14, 2, SG, KCF>(sh, nsteps, lane, kc);
+    helper_steps<5, 13, 2, SG, KCF>(sh, nsteps, lane, kc);
   }
 }
 
