@@ -537,7 +537,7 @@ cholmod_plan select_plan(const cholmod_desc* descs, int64_t count) {
 int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_bytes,
                   int64_t* d_info, hipStream_t st, void* stage, size_t stage_bytes,
                   const std::function<int(int64_t)>* after_step, int64_t* d_done,
-                  const cholmod_plan* plan) {
+                  const cholmod_plan* plan, hipEvent_t staged) {
   BatchPlan P;
   const cholmod_plan lp = plan ? *plan : default_plan();
   if (!plan_ok(lp)) return CHOLMOD_ERR_ARG;
@@ -561,6 +561,7 @@ int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_
   write_tables(P, h);
   if (hipMemcpyAsync(ws, h, P.table_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
     return CHOLMOD_ERR_HIP;
+  if (staged && hipEventRecord(staged, st) != hipSuccess) return CHOLMOD_ERR_HIP;
   const BatchFactor* d_fac = (const BatchFactor*)ws;
   const BatchEntry* d_ent = (const BatchEntry*)((char*)ws + P.off_ent);
   if (after_step == nullptr) {
@@ -1164,7 +1165,8 @@ int cholmod_update_batched_plan(const cholmod_desc* descs, int64_t count,
   std::lock_guard<std::mutex> lk(g_mu);
   if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
   DevWs& d = g_ws[dev];
-  // the pinned staging buffer is reused: wait for its previous upload
+  // the pinned staging buffer is reused: wait for its previous upload (not
+  // for the previous batch, so that this batch's planning overlaps it)
   if (d.stage_pending) {
     if (hipEventSynchronize(d.stage_done) != hipSuccess) return CHOLMOD_ERR_HIP;
     d.stage_pending = false;
@@ -1180,10 +1182,10 @@ int cholmod_update_batched_plan(const cholmod_desc* descs, int64_t count,
   }
   hipStream_t st = (hipStream_t)stream;
   const int rc = enqueue_batch(descs, count, ws, ws_bytes, d_info, st, d.stage, d.stage_bytes,
-                               nullptr, nullptr, &lp);
-  if (rc) return rc;
-  if (hipEventRecord(d.stage_done, st) != hipSuccess) return CHOLMOD_ERR_HIP;
+                               nullptr, nullptr, &lp, d.stage_done);
+  // the event may have been recorded even if a later launch failed
   d.stage_pending = true;
+  if (rc) return rc;
   return CHOLMOD_OK;
 }
 

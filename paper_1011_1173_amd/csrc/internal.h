@@ -32,11 +32,14 @@ int64_t batch_steps_of(const cholmod_desc& d);
 // `st`); a non-zero return stops and is returned.
 // plan (or null: the default plan) chooses the schedule of a batch without
 // after_step and the queued launch's shape; a batch with d_done must be
-// queued.
+// queued.  staged (or null) is recorded on `st` right after the upload of
+// the tables from `stage`: once it has completed, `stage` may be rewritten
+// while the batch still runs.
 int enqueue_batch(const cholmod_desc* descs, int64_t count, void* ws, size_t ws_bytes,
                   int64_t* d_info, hipStream_t st, void* stage, size_t stage_bytes,
                   const std::function<int(int64_t)>* after_step = nullptr,
-                  int64_t* d_done = nullptr, const cholmod_plan* plan = nullptr);
+                  int64_t* d_done = nullptr, const cholmod_plan* plan = nullptr,
+                  hipEvent_t staged = nullptr);
 
 // Workspace that fits a batch under either schedule; 0 if invalid.
 size_t batch_workspace_bytes_any(const cholmod_desc* descs, int64_t count);

@@ -103,6 +103,39 @@ def test_batched_uneven_pool(orc):
         assert np.array_equal(single[i], batched[i]), i
 
 
+def test_batches_back_to_back_equal_batches_in_turn(orc):
+    """Two batches enqueued without waiting (the second is planned and its
+    tables uploaded from the reused pinned buffer while the first may still
+    run; factors 6..11 are in both) give what the two batches give one
+    after the other, bit for bit."""
+    import paper_1011_1173_amd as chm
+    rng = np.random.default_rng(11)
+    print_case("batched-back-to-back", count=18)
+    cases = [make_case(orc, int(rng.integers(64, 1500)), int(rng.integers(1, 33)), 1, False,
+                       7500 + i) for i in range(18)]
+    Vb = [problem(L.shape[0], int(rng.integers(1, 33)), 7600 + i)[1]
+          for i, (L, _) in enumerate(cases)]
+    A, B = range(0, 12), range(6, 18)
+
+    def run(wait):
+        Ls = [to_dev(L, False) for L, _ in cases]
+        VA = [to_dev(cases[i][1], False) for i in A]
+        VB = [to_dev(Vb[i], False) for i in B]
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            pa = chm.update_batched_async([Ls[i] for i in A], VA, [1] * len(A), stream=st)
+            sa = pa.statuses() if wait else None
+            pb = chm.update_batched_async([Ls[i] for i in B], VB, [1] * len(B), stream=st)
+        sa = sa if wait else pa.statuses()
+        sb = pb.statuses()
+        assert all(x[0] == 0 for x in sa + sb), (sa, sb)
+        return [L.cpu().numpy() for L in Ls]
+
+    inturn, b2b = run(True), run(False)
+    for i in range(18):
+        assert np.array_equal(inturn[i], b2b[i]), i
+
+
 def test_every_tuned_plan_equals_single_bitwise(orc):
     """Every launch plan the autotuner may pick (queued with block maps: fewer
     workgroups, factor-major order, other poll levels) and the plans outside
