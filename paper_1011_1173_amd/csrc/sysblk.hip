@@ -557,15 +557,21 @@ __device__ __forceinline__ int map_stage(SbLds& sh, const double* Mb, double* ds
     v[i] = src[i * 64];
     full &= v[i] != kMapEmpty;
   }
+  // the last entry of the quarter (one request per wave and poll) until it is
+  // written, then the whole quarter until no entry is empty
+  const uint64_t* last = reinterpret_cast<const uint64_t*>(Mb + (q + 1) * kMapPerWave) - 1;
   while (!__all(full)) {
-    full = true;
+    if (__all(__hip_atomic_load(const_cast<uint64_t*>(last), __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT) != kMapEmpty)) {
+      full = true;
 #pragma unroll
-    for (int i = 0; i < kN; ++i) {
-      v[i] = __hip_atomic_load(const_cast<uint64_t*>(src + i * 64), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-      full &= v[i] != kMapEmpty;
+      for (int i = 0; i < kN; ++i) {
+        v[i] = __hip_atomic_load(const_cast<uint64_t*>(src + i * 64), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        full &= v[i] != kMapEmpty;
+      }
+      if (__all(full)) break;
     }
-    if (__all(full)) break;
     if (wall_clock64() > deadline) {
       sh.tmo = 1;
       return kMapRot;
