@@ -972,7 +972,10 @@ __device__ __forceinline__ void helper_steps_pub(SbLds& sh, int nsteps, int lane
   double st[kSt];
   helper_init<15, 1>(sh, st, lane);
   __syncthreads();
-  int q = 0;
+  // rows [rn, rn + 4) are read after step tn - 1, in groups of four as
+  // each group is complete and the block's last four rows one by one, so
+  // that the next owner can apply rows 60..62 before row 63 arrives
+  int rn = 0, tn = pub ? 3 + kc : -1;
   bool have = false;
   RotRec rec;
   GRec<ST>* dst = T;
@@ -981,12 +984,14 @@ __device__ __forceinline__ void helper_steps_pub(SbLds& sh, int nsteps, int lane
     if (have) publish_record(dst, rec);
     have = false;
     __syncthreads();
-    if (pub && q < kBR / 4 && t + 1 == 4 * q + 3 + kc) {
-      const int r = 4 * q + (lane >> 4), m = lane & 15;
+    if (t + 1 == tn) {
+      const bool one = rn >= kBR - 4;
+      const int r = rn + (one ? 0 : lane >> 4), m = lane & 15;
       rec = sh.R[r + kPad][m];
       dst = T + (pc + r) * kKP + m;
-      have = m < kc;
-      ++q;
+      have = m < kc && (!one || lane < 16);
+      rn += one ? 1 : 4;
+      tn = rn >= kBR ? -1 : rn < kBR - 4 ? rn + 3 + kc : rn + kc;
     }
   }
   if (have) publish_record(dst, rec);
