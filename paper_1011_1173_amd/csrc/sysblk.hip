@@ -1844,8 +1844,16 @@ __global__ __launch_bounds__(kThreads) void k_sb_qbatch(const BatchFactor* __res
     const QItem it = items[t];
     const BatchFactor B = fac[it.f];
     qbatch_item(sh, B, it.j, poll);  // ends with a barrier: every wave's stores are issued
+    if (B.done != nullptr) {
+      // Once the factor's last item is counted, the host may hand the factor
+      // to a batch that runs beside this one.  Every wave waits for its own
+      // stores and writes them back device-wide before the count goes down:
+      // the barrier above only orders their issue, and one wave's fence does
+      // not wait for stores the other waves still have in flight.
+      __threadfence();
+      __syncthreads();
+    }
     if (threadIdx.x == 0 && B.done != nullptr) {
-      __threadfence();  // the workgroup's stores, device-wide
       if (__hip_atomic_fetch_add(B.left, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1) {
         const int64_t info =
             __hip_atomic_load(B.info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
