@@ -304,25 +304,32 @@ __device__ __forceinline__ void w2x2_load(ST (&w)[kOwnCols], const ST* __restric
 }
 
 // One sub-step s of an apply lane: records qc (row s - h); loads the next
-// records into qn.  The tile is in LDS at `tile` with row stride LD.  Row
-// s + 1 of the tile, which the lanes of h = 0 take at the next sub-step, is
-// read at the start and becomes the fill value of the shift at the end, so
-// its load latency is hidden and no register is copied for it (every lane
-// reads it: one LDS broadcast per column pair costs less than masking the
-// others off).  WRITE: the sub-step may finish a row (s >= hf; before, the
-// lanes of h = hf still hold rows < 0), which lane h = hf stores.  DRAIN
-// (s >= 63): the lanes of h = 0 enter rows past the tile, whose records are
-// identity; they take 0, which such a rotation passes through exactly (a
-// value read past the tile could be a NaN, and 0 * NaN would spoil V).
-// Callers alternate two record sets, so that nothing is copied between
-// sub-steps.
+// records into qn.  The tile is in LDS at `tile` with row stride LD.  fc is
+// the fill value of this sub-step's shift: row s + 1 of the tile, which the
+// lanes of h = 0 take at the next sub-step; the sub-step reads row s + 2 into
+// fn for the next one, so that each fill read has a whole sub-step to land
+// (every lane reads it: one LDS broadcast per column pair costs less than
+// masking the others off).  WRITE: the sub-step may finish a row (s >= hf;
+// before, the lanes of h = hf still hold rows < 0), which lane h = hf stores;
+// the rows read ahead are never the ones written.  DRAIN (s >= 63): the lanes
+// of h = 0 enter rows past the tile, whose records are identity; they take 0,
+// which such a rotation passes through exactly (a value read past the tile
+// could be a NaN, and 0 * NaN would spoil V).  Callers alternate two record
+// and fill sets, so that nothing is copied between sub-steps.
 template <int SG, typename ST, int LD, bool WRITE, bool DRAIN>
 __device__ __forceinline__ void sub2x2(ST* tile, const RotRec* rp, int s, int h, int c0,
                                        int hf, bool first, ST (&w)[kOwnCols], ST (&xin)[2],
-                                       const RotRec (&qc)[2], RotRec (&qn)[2]) {
-  ST fill[2];
+                                       const RotRec (&qc)[2], RotRec (&qn)[2],
+                                       const ST (&fc)[2], ST (&fn)[2]) {
+  if (DRAIN) {
+    fn[0] = fn[1] = (ST)0;
+  } else {
+    // row s + 2 (row 63 when that is past the tile: the next sub-step is
+    // then a drain sub-step, which takes 0 instead)
+    const int rn = imin(s + 2, kBR - 1);
 #pragma unroll
-  for (int u = 0; u < 2; ++u) fill[u] = DRAIN ? (ST)0 : tile[(s + 1) * LD + c0 + u];
+    for (int u = 0; u < 2; ++u) fn[u] = tile[rn * LD + c0 + u];
+  }
   // s + 1 <= 71: record rows up to 87
   qn[0] = rp[(s + 1) * kKP];
   qn[1] = rp[(s + 1) * kKP + 1];
@@ -342,7 +349,7 @@ __device__ __forceinline__ void sub2x2(ST* tile, const RotRec* rp, int s, int h,
     for (int u = 0; u < 2; ++u) tile[r * LD + c0 + u] = first ? x1[u] : x2[u];
   }
 #pragma unroll
-  for (int u = 0; u < 2; ++u) xin[u] = sb_shr<2>(x2[u], fill[u]);
+  for (int u = 0; u < 2; ++u) xin[u] = sb_shr<2>(x2[u], DRAIN ? (ST)0 : fc[u]);
 }
 
 // Sub-steps [s, lim) of an apply lane (s is advanced); qa holds the records
@@ -352,24 +359,35 @@ __device__ __forceinline__ void sub2x2_run(ST* tile, const RotRec* rp, int& s, i
                                            int c0, int hf, bool first, ST (&w)[kOwnCols],
                                            ST (&xin)[2], RotRec (&qa)[2]) {
   RotRec qb[2];
+  // the fill of sub-step s: row s + 1 of the tile (unused by drain sub-steps)
+  ST fa[2], fb[2];
+  {
+    const int r1 = imin(s + 1, kBR - 1);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) fa[u] = tile[r1 * LD + c0 + u];
+  }
   for (; s < lim && s < hf; ++s) {  // no row is finished yet
-    sub2x2<SG, ST, LD, false, false>(tile, rp, s, h, c0, hf, first, w, xin, qa, qb);
+    sub2x2<SG, ST, LD, false, false>(tile, rp, s, h, c0, hf, first, w, xin, qa, qb, fa, fb);
     qa[0] = qb[0];
     qa[1] = qb[1];
+    fa[0] = fb[0];
+    fa[1] = fb[1];
   }
   const int lmain = imin(lim, kBR - 1);  // sub-steps whose next row is in the tile
   for (; s + 2 <= lmain; s += 2) {
-    sub2x2<SG, ST, LD, true, false>(tile, rp, s, h, c0, hf, first, w, xin, qa, qb);
-    sub2x2<SG, ST, LD, true, false>(tile, rp, s + 1, h, c0, hf, first, w, xin, qb, qa);
+    sub2x2<SG, ST, LD, true, false>(tile, rp, s, h, c0, hf, first, w, xin, qa, qb, fa, fb);
+    sub2x2<SG, ST, LD, true, false>(tile, rp, s + 1, h, c0, hf, first, w, xin, qb, qa, fb, fa);
   }
   if (s < lmain) {
-    sub2x2<SG, ST, LD, true, false>(tile, rp, s, h, c0, hf, first, w, xin, qa, qb);
+    sub2x2<SG, ST, LD, true, false>(tile, rp, s, h, c0, hf, first, w, xin, qa, qb, fa, fb);
     ++s;
     qa[0] = qb[0];
     qa[1] = qb[1];
+    fa[0] = fb[0];
+    fa[1] = fb[1];
   }
   for (; s < lim; ++s) {  // the drain: at most hf + 1 sub-steps
-    sub2x2<SG, ST, LD, true, true>(tile, rp, s, h, c0, hf, first, w, xin, qa, qb);
+    sub2x2<SG, ST, LD, true, true>(tile, rp, s, h, c0, hf, first, w, xin, qa, qb, fa, fb);
     qa[0] = qb[0];
     qa[1] = qb[1];
   }
