@@ -559,10 +559,9 @@ __device__ __forceinline__ void map_build(SbLds& sh, int kc, double* __restrict_
 // more (it polls, sleeping between polls; past the deadline it sets sh.tmo
 // and gives up).  Returns kMapOk, or kMapRot for a map published as
 // unusable (then nothing is copied); every staging wave finds the same.
-// The first read goes through the caches: an entry is written once per
-// launch, so a cached copy is either still kMapEmpty or final, and the
-// owners on one XCD then share one fetch of the map; only a read that still
-// finds empty entries polls with device-scope loads.
+// Every read is a device-scope load: the map region of a batch may hold an
+// earlier batch's map (served batches reuse the workspace arena), and a
+// cached copy of such a line is the one read that could see it.
 constexpr int kMapPerWave = kMapElems / 4;  // 1216 = 19 x 64
 __device__ __forceinline__ int map_stage(SbLds& sh, const double* Mb, double* dst,
                                          int64_t deadline, int q, int lane) {
@@ -572,7 +571,8 @@ __device__ __forceinline__ int map_stage(SbLds& sh, const double* Mb, double* ds
   bool full = true;
 #pragma unroll
   for (int i = 0; i < kN; ++i) {
-    v[i] = src[i * 64];
+    v[i] = __hip_atomic_load(const_cast<uint64_t*>(src + i * 64), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
     full &= v[i] != kMapEmpty;
   }
   // the last entry of the quarter (one request per wave and poll) until it is
@@ -603,7 +603,7 @@ __device__ __forceinline__ int map_stage(SbLds& sh, const double* Mb, double* ds
 }
 
 // map_stage without waiting: kMapWait (nothing copied) if an entry of wave
-// q's quarter is still empty after a second, device-scope read.
+// q's quarter is still empty.
 __device__ __forceinline__ int map_try_stage(SbLds& sh, const double* Mb, double* dst, int q,
                                              int lane) {
   constexpr int kN = kMapPerWave / 64;
@@ -612,19 +612,11 @@ __device__ __forceinline__ int map_try_stage(SbLds& sh, const double* Mb, double
   bool full = true;
 #pragma unroll
   for (int i = 0; i < kN; ++i) {
-    v[i] = src[i * 64];
+    v[i] = __hip_atomic_load(const_cast<uint64_t*>(src + i * 64), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
     full &= v[i] != kMapEmpty;
   }
-  if (!__all(full)) {
-    full = true;
-#pragma unroll
-    for (int i = 0; i < kN; ++i) {
-      v[i] = __hip_atomic_load(const_cast<uint64_t*>(src + i * 64), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-      full &= v[i] != kMapEmpty;
-    }
-    if (!__all(full)) return kMapWait;
-  }
+  if (!__all(full)) return kMapWait;
   if (__builtin_amdgcn_readfirstlane((int)(v[0] == kMapRotate))) return kMapRot;
 #pragma unroll
   for (int i = 0; i < kN; ++i) dst[q * kMapPerWave + i * 64 + lane] = __builtin_bit_cast(double, v[i]);

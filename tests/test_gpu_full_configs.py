@@ -93,8 +93,11 @@ def test_served_pool_equals_sequential(orc):
         st, _, _ = chm.update_async(ref[f], prior[f], +1).status()
         assert st == 0
     served = [L.clone() for L in ref]
+    waited = [L.clone() for L in ref]  # the same sequence, each call waited for
     for f, V, s in reqs:
         chm.update_async(ref[f], V, s)
+    for f, V, s in reqs:
+        assert chm.update_async(waited[f], V, s).status()[0] == 0
     torch.cuda.synchronize()
     with chm.Server(ws_bytes=1 << 30, max_batch=64) as srv:
         ids = [srv.add_factor(L) for L in served]
@@ -102,8 +105,19 @@ def test_served_pool_equals_sequential(orc):
         srv.drain()
         res = [srv.poll(t) for t in tickets]
     assert all(st == 0 for st, _ in res), [r for r in res if r[0] != 0][:4]
+
+    def where(a, b):
+        d = (a - b).abs()
+        i = int(torch.nan_to_num(d, nan=float("inf")).argmax())
+        return "max |diff| %.3e at (%d, %d), %d elements differ, NaN %d / %d" % (
+            float(torch.nan_to_num(d, nan=float("inf")).max()), i // a.shape[1], i % a.shape[1],
+            int((a != b).sum()), int(torch.isnan(a).sum()), int(torch.isnan(b).sum()))
+
     for f in range(nf):
-        assert torch.equal(ref[f], served[f]), "factor %d (n=%d)" % (f, ns[f])
+        assert torch.equal(ref[f], waited[f]), "reference, factor %d (n=%d): %s" % (
+            f, ns[f], where(ref[f], waited[f]))
+        assert torch.equal(ref[f], served[f]), "factor %d (n=%d, k %s): %s" % (
+            f, ns[f], [V.shape[1] for g, V, _ in reqs if g == f], where(ref[f], served[f]))
     # every factor with n <= 4096 against the oracle: the prior V, then its
     # request pairs in order, from the generator's factor
     small = [f for f in range(nf) if ns[f] <= 4096]
