@@ -84,6 +84,43 @@ def test_batched_failure_stays_in_its_factor(orc):
     assert np.array_equal(single[1][:r], batched[1][:r])
 
 
+def test_batch_after_failed_batch_in_the_same_workspace(orc):
+    """A batch whose workspace last held another batch's block maps (the same
+    layout, so every map region is reused), among them the unusable maps of
+    downdates that fail early, gives the single-factor results bit for bit."""
+    import paper_1011_1173_amd as chm
+    n, k, r = 1024, 16, 100  # 16 blocks: blocks 0..9 get maps
+    print_case("batched-reused-workspace", n=n, k=k)
+    first, second = [], []
+    for i in range(6):
+        if i % 2 == 0:  # fails at row r: the maps of later blocks are unusable
+            Lf, _ = problem(n, 1, seed=900 + i)
+            Vf = np.zeros((n, k))
+            Vf[:, 0] = 2.0 * Lf[r, :n]
+            first.append((Lf, Vf, -1))
+        else:
+            L, V = problem(n, k, seed=900 + i)
+            first.append((L, V, 1))
+        L, V = problem(n, k, seed=950 + i)
+        second.append((L, V, 1))
+    Ls = [to_dev(L, False) for L, _, _ in first]
+    ws_bytes = int(chm._native.load().cholmod_workspace_bytes_batched(
+        chm._descs(Ls, [to_dev(V, False) for _, V, _ in first], [s for _, _, s in first])[0],
+        len(first)))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    st1 = chm.update_batched_async(Ls, [to_dev(V, False) for _, V, _ in first],
+                                   [s for _, _, s in first], workspace=ws).statuses()
+    assert [x[0] == orc.NOT_PD for x in st1] == [i % 2 == 0 for i in range(6)], st1
+    Ls2 = [to_dev(L, False) for L, _, _ in second]
+    st2 = chm.update_batched_async(Ls2, [to_dev(V, False) for _, V, _ in second],
+                                   [1] * 6, workspace=ws).statuses()
+    assert all(x[0] == 0 for x in st2), st2
+    for i, (L, V, sg) in enumerate(second):
+        Ld, Vd = to_dev(L, False), to_dev(V, False)
+        assert chm.update_async(Ld, Vd, sg).status()[0] == 0
+        assert torch.equal(Ld, Ls2[i]), i
+
+
 def test_batched_uneven_pool(orc):
     """A smaller pool in the shape of the batched workload: n ~ U{64..1024},
     k ~ U{1..32}, half updates and half downdates, FP64 and FP32 storage."""
