@@ -1792,7 +1792,9 @@ __global__ __launch_bounds__(kThreads) void k_sb_queue(OwnF<ST> F, int nitems,
     const int j = sh.tk;
     __syncthreads();
     if (j >= nitems) break;
-    owner_item<SG, ST, true>(sh, F, j, 2);
+    // every owner polls with the short sleep: one factor has at most one
+    // owner per CU, and sleeping longer between polls measured slower
+    owner_item<SG, ST, true>(sh, F, j, 0);
   }
 }
 
